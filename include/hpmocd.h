@@ -1,0 +1,150 @@
+/*
+ * hpmocd.h - C ABI of the MI355X (gfx950) implementation of the HP-MOCD community search
+ * (arXiv 2506.01752): an NSGA-II over node-label partitions of an undirected, unweighted
+ * graph that minimises the two objectives of section 4.1 (eq. "objectives").
+ *
+ * Conventions (every entry point):
+ *  - Status is an int: HPMOCD_OK (0) or a negative HPMOCD_ERR_* code; hpmocd_strerror()
+ *    names it. No C++ exception crosses this boundary. Output arguments are written only
+ *    on success.
+ *  - Host inputs are read during the call and copied; the caller keeps ownership.
+ *  - Device workspace and the HIP stream (a hipStream_t passed as void*, NULL = the null
+ *    stream) belong to the caller; the library launches its kernels on that stream and
+ *    synchronises it before returning results to the host.
+ *  - Objects returned through an out-pointer (graphs, fronts) belong to the library until
+ *    released with their *_destroy / *_free function.
+ *  - Results are deterministic: a run is a pure function of (graph, params).
+ */
+#ifndef HPMOCD_H
+#define HPMOCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HPMOCD_OK 0
+#define HPMOCD_ERR_ARG -1        /* null pointer or parameter out of range */
+#define HPMOCD_ERR_CSR_ASYM -2   /* arc (u,v) present without (v,u) */
+#define HPMOCD_ERR_SELF_LOOP -3  /* arc (v,v); section 2.1 excludes self-loops */
+#define HPMOCD_ERR_DUP_EDGE -4   /* repeated arc; the graph is simple (section 2.1) */
+#define HPMOCD_ERR_RANGE -5      /* row_ptr not monotone from 0, or a column outside [0,n) */
+#define HPMOCD_ERR_EMPTY -6      /* no edge: f1 = 0/0 is undefined */
+#define HPMOCD_ERR_TOO_LARGE -7  /* (2m)^2 > 2^53: f2's denominator would not be exact */
+#define HPMOCD_ERR_WORKSPACE -8  /* workspace smaller than the size the library asked for */
+#define HPMOCD_ERR_HIP -9        /* a HIP runtime call failed */
+#define HPMOCD_ERR_BUDGET -10    /* request does not fit the device-memory budget */
+#define HPMOCD_ERR_NOMEM -11     /* host allocation failed */
+
+/* Largest population: the selection kernels rank 2 * pop_size points in one workgroup. */
+#define HPMOCD_MAX_POP 512
+/* Largest ensemble (parents per child, E_S of Alg. 1). */
+#define HPMOCD_MAX_PARENTS 8
+
+/* Graph G = (V, E) of section 2.1: simple, undirected, unweighted. Opaque; device resident. */
+typedef struct hpmocd_graph hpmocd_graph;
+
+/* Parameters of Alg. 1: HP-MOCD(G, N_p, T, C_P, M_P, E_S) plus the seed of the counter-based
+ * random stream (Philox4x32-10 keyed by the seed, counter = (node or slot, individual,
+ * generation, purpose)). */
+typedef struct {
+    int32_t pop_size;          /* N_p, 1 .. HPMOCD_MAX_POP */
+    int32_t generations;       /* T >= 0 */
+    double crossover_p;        /* C_P in [0,1]: majority-vote crossover happens w.p. C_P (Alg. 2) */
+    double mutation_p;         /* M_P in [0,1]: per-node neighbour-plurality mutation (sec. 4.3.2) */
+    int32_t parents_per_child; /* E_S, 1 .. HPMOCD_MAX_PARENTS (the paper uses 4) */
+    uint64_t seed;
+} hpmocd_params;
+
+/* First front F_1 of the final population (Alg. 1, phase 4), host memory owned by the
+ * library. Rows are in crowded-comparison order (rank, then crowding distance descending,
+ * then position); identical partitions are kept. Labels are node ids in [0, n): node v's
+ * community is named by the id of some node. */
+typedef struct {
+    int32_t n_solutions;       /* k = |F_1| >= 1 */
+    int32_t n_nodes;           /* n */
+    int32_t *labels;           /* k x n, row-major */
+    int64_t *intra_arcs;       /* A = 2 sum_c |E(c)| per solution */
+    int64_t *sum_deg_sq;       /* S = sum_c (sum_{v in c} deg v)^2 per solution */
+    double *f1;                /* (2m - A) / 2m, one binary64 division (eq. objectives) */
+    double *f2;                /* S / (2m)^2, one binary64 division */
+    int32_t selected;          /* Alg. 3: first index maximising (1 - f1) - f2 */
+} hpmocd_front;
+
+/* Per-generation observables handed to a trace callback (host copies, valid during the
+ * callback only). At g = 0 they describe the initial population; at g >= 1 the population
+ * after environmental selection of generation g, in selection order. rank/crowd are those
+ * computed at the start of generation g on P^(g-1) (NULL at g = 0), in that step's order. */
+typedef struct {
+    int32_t g, pop_size, n_nodes;
+    const int32_t *labels;     /* pop_size x n, row-major */
+    const int64_t *A, *S;
+    const double *f1, *f2;
+    const int32_t *rank;
+    const double *crowd;
+} hpmocd_state_view;
+
+typedef void (*hpmocd_trace_fn)(const hpmocd_state_view *state, void *user);
+
+/* Stream-ordered timings of a run (milliseconds of device time, from HIP events recorded on
+ * the caller's stream). Kernel-group times are filled only with HPMOCD_TIME_KERNELS. */
+typedef struct {
+    double total_ms;           /* init through front extraction */
+    double loop_ms;            /* generations 1..T */
+    double fitness_ms;         /* edge-scan fitness kernels (all launches) */
+    double sweep_ms;           /* community-degree square-sum kernels */
+    double variation_ms;       /* crossover + mutation kernels */
+    double select_ms;          /* ranking / crowding / selection kernels */
+    int64_t fitness_launches;  /* number of edge-scan launches */
+    int64_t individual_evals;  /* N_p (T + 1) */
+} hpmocd_profile;
+
+#define HPMOCD_NO_GRAPH 1      /* launch each kernel (no hipGraph replay of the loop) */
+#define HPMOCD_TIME_KERNELS 2  /* record events around every kernel group (implies NO_GRAPH) */
+
+/* Builds the device graph from a symmetric CSR (row_ptr[n+1], col[row_ptr[n]]).
+ * Validates it (codes above; section 2.1 requires a simple undirected graph), sorts every
+ * adjacency list ascending, and copies it to the current HIP device (synchronously).
+ * n >= 1; isolated nodes are allowed. */
+int hpmocd_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *col,
+                        hpmocd_graph **out);
+void hpmocd_graph_destroy(hpmocd_graph *g);
+/* n, number of arcs (2m) and the largest degree. Any out-pointer may be NULL. */
+int hpmocd_graph_info(const hpmocd_graph *g, int32_t *n, int64_t *arcs, int32_t *max_deg);
+
+/* Bytes of device workspace hpmocd_run needs for these parameters (256-byte aligned). */
+int hpmocd_workspace_size(const hpmocd_graph *g, const hpmocd_params *p, size_t *bytes);
+
+/* Alg. 1 end to end on the device: initialisation, T generations of tournament ->
+ * crossover (Alg. 2) -> mutation (sec. 4.3.2) -> evaluation (eq. objectives) ->
+ * environmental selection, then the first front and the Alg. 3 choice. d_workspace must be
+ * device memory of at least hpmocd_workspace_size bytes; its contents on entry do not
+ * matter. The front is returned in *out (free with hpmocd_front_free). */
+int hpmocd_run(const hpmocd_graph *g, const hpmocd_params *p, void *d_workspace,
+               size_t ws_bytes, void *stream, hpmocd_front **out);
+
+/* hpmocd_run with options: flags (HPMOCD_NO_GRAPH, HPMOCD_TIME_KERNELS), an optional profile
+ * to fill, and an optional per-generation trace callback (forces NO_GRAPH and copies the
+ * population to the host every generation: tests only). Results equal hpmocd_run's. */
+int hpmocd_run_ex(const hpmocd_graph *g, const hpmocd_params *p, void *d_workspace,
+                  size_t ws_bytes, void *stream, int flags, hpmocd_profile *profile,
+                  hpmocd_trace_fn trace, void *user, hpmocd_front **out);
+
+void hpmocd_front_free(hpmocd_front *f);
+
+/* Fitness alone (eq. objectives) for n_ind partitions given as device memory, row-major
+ * n_ind x n int32 labels in [0, n) (values outside are an error the kernel cannot report:
+ * the caller guarantees the range). Writes A, S, f1, f2 (host arrays of n_ind). */
+int hpmocd_eval_workspace_size(const hpmocd_graph *g, int32_t n_ind, size_t *bytes);
+int hpmocd_eval(const hpmocd_graph *g, const int32_t *d_labels, int32_t n_ind,
+                void *d_workspace, size_t ws_bytes, void *stream, int64_t *A, int64_t *S,
+                double *f1, double *f2, double *kernel_ms);
+
+const char *hpmocd_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPMOCD_H */

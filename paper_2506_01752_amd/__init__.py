@@ -1,0 +1,280 @@
+"""MI355X (gfx950) implementation of the HP-MOCD community search (arXiv 2506.01752).
+
+A thin ctypes binding of ``libhpmocd.so`` (C ABI declared in ``include/hpmocd.h``). Every
+step of the method runs in the library's HIP kernels; this module only marshals arguments.
+PyTorch supplies the device workspace and the stream. There is no CPU fallback: when the
+library is missing, importing ``lib()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhpmocd.so")
+
+OK = 0
+ERR = {
+    -1: "ERR_ARG", -2: "ERR_CSR_ASYM", -3: "ERR_SELF_LOOP", -4: "ERR_DUP_EDGE",
+    -5: "ERR_RANGE", -6: "ERR_EMPTY", -7: "ERR_TOO_LARGE", -8: "ERR_WORKSPACE",
+    -9: "ERR_HIP", -10: "ERR_BUDGET", -11: "ERR_NOMEM",
+}
+MAX_POP = 512
+MAX_PARENTS = 8
+NO_GRAPH = 1
+TIME_KERNELS = 2
+
+# every entry point that include/hpmocd.h declares
+EXPORTS = [
+    "hpmocd_graph_create", "hpmocd_graph_destroy", "hpmocd_graph_info",
+    "hpmocd_workspace_size", "hpmocd_run", "hpmocd_run_ex", "hpmocd_front_free",
+    "hpmocd_eval_workspace_size", "hpmocd_eval", "hpmocd_strerror",
+]
+
+
+class HpmocdError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {ERR.get(status, status)} ({_strerror(status)})")
+
+
+class Params(C.Structure):
+    _fields_ = [("pop_size", C.c_int32), ("generations", C.c_int32),
+                ("crossover_p", C.c_double), ("mutation_p", C.c_double),
+                ("parents_per_child", C.c_int32), ("seed", C.c_uint64)]
+
+
+class _Front(C.Structure):
+    _fields_ = [("n_solutions", C.c_int32), ("n_nodes", C.c_int32),
+                ("labels", C.POINTER(C.c_int32)), ("intra_arcs", C.POINTER(C.c_int64)),
+                ("sum_deg_sq", C.POINTER(C.c_int64)), ("f1", C.POINTER(C.c_double)),
+                ("f2", C.POINTER(C.c_double)), ("selected", C.c_int32)]
+
+
+class _View(C.Structure):
+    _fields_ = [("g", C.c_int32), ("pop_size", C.c_int32), ("n_nodes", C.c_int32),
+                ("labels", C.POINTER(C.c_int32)),
+                ("A", C.POINTER(C.c_int64)), ("S", C.POINTER(C.c_int64)),
+                ("f1", C.POINTER(C.c_double)), ("f2", C.POINTER(C.c_double)),
+                ("rank", C.POINTER(C.c_int32)), ("crowd", C.POINTER(C.c_double))]
+
+
+class Profile(C.Structure):
+    _fields_ = [("total_ms", C.c_double), ("loop_ms", C.c_double),
+                ("fitness_ms", C.c_double), ("sweep_ms", C.c_double),
+                ("variation_ms", C.c_double), ("select_ms", C.c_double),
+                ("fitness_launches", C.c_int64), ("individual_evals", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_TRACE = C.CFUNCTYPE(None, C.POINTER(_View), C.c_void_p)
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        i32p, i64p, f64p, vp = (C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                C.POINTER(C.c_double), C.c_void_p)
+        L.hpmocd_graph_create.argtypes = [C.c_int32, i32p, i32p, C.POINTER(vp)]
+        L.hpmocd_graph_destroy.argtypes = [vp]
+        L.hpmocd_graph_destroy.restype = None
+        L.hpmocd_graph_info.argtypes = [vp, i32p, i64p, i32p]
+        L.hpmocd_workspace_size.argtypes = [vp, C.POINTER(Params), C.POINTER(C.c_size_t)]
+        L.hpmocd_run.argtypes = [vp, C.POINTER(Params), vp, C.c_size_t, vp,
+                                 C.POINTER(C.POINTER(_Front))]
+        L.hpmocd_run_ex.argtypes = [vp, C.POINTER(Params), vp, C.c_size_t, vp, C.c_int,
+                                    C.POINTER(Profile), _TRACE, vp,
+                                    C.POINTER(C.POINTER(_Front))]
+        L.hpmocd_front_free.argtypes = [C.POINTER(_Front)]
+        L.hpmocd_front_free.restype = None
+        L.hpmocd_eval_workspace_size.argtypes = [vp, C.c_int32, C.POINTER(C.c_size_t)]
+        L.hpmocd_eval.argtypes = [vp, vp, C.c_int32, vp, C.c_size_t, vp, i64p, i64p, f64p, f64p,
+                                  f64p]
+        L.hpmocd_strerror.argtypes = [C.c_int]
+        L.hpmocd_strerror.restype = C.c_char_p
+        for name in EXPORTS:
+            if name not in ("hpmocd_graph_destroy", "hpmocd_front_free", "hpmocd_strerror"):
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _strerror(status: int) -> str:
+    try:
+        return lib().hpmocd_strerror(status).decode()
+    except Exception:  # pragma: no cover - only used for messages
+        return "?"
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise HpmocdError(status, what)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def graph_create_status(n: int, row_ptr, col) -> int:
+    """Runs hpmocd_graph_create and returns its status (destroying the graph on success).
+    Validation happens before any device call, so this also works without a GPU."""
+    rp, cl = _i32(row_ptr), _i32(col)
+    h = C.c_void_p()
+    st = lib().hpmocd_graph_create(n, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                                   cl.ctypes.data_as(C.POINTER(C.c_int32)) if cl.size else None,
+                                   C.byref(h))
+    if st == OK:
+        lib().hpmocd_graph_destroy(h)
+    return st
+
+
+class Graph:
+    """Device-resident simple undirected graph (hpmocd_graph)."""
+
+    def __init__(self, row_ptr, col):
+        rp, cl = _i32(row_ptr), _i32(col)
+        self._h = C.c_void_p()
+        _check(lib().hpmocd_graph_create(len(rp) - 1, rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         cl.ctypes.data_as(C.POINTER(C.c_int32)),
+                                         C.byref(self._h)), "hpmocd_graph_create")
+        n, arcs, md = C.c_int32(), C.c_int64(), C.c_int32()
+        _check(lib().hpmocd_graph_info(self._h, C.byref(n), C.byref(arcs), C.byref(md)),
+               "hpmocd_graph_info")
+        self.n, self.arcs, self.max_deg = n.value, arcs.value, md.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().hpmocd_graph_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+@dataclass
+class Front:
+    labels: np.ndarray   # (k, n) int32
+    A: np.ndarray        # intra arcs, int64
+    S: np.ndarray        # sum of squared community degrees, int64
+    f1: np.ndarray
+    f2: np.ndarray
+    selected: int
+
+
+@dataclass
+class State:
+    g: int
+    labels: np.ndarray
+    A: np.ndarray
+    S: np.ndarray
+    f1: np.ndarray
+    f2: np.ndarray
+    rank: np.ndarray | None
+    crowd: np.ndarray | None
+
+
+def make_params(pop_size=100, generations=100, crossover_p=0.9, mutation_p=0.1,
+                parents_per_child=4, seed=0) -> Params:
+    return Params(pop_size, generations, crossover_p, mutation_p, parents_per_child, seed)
+
+
+def workspace_size(graph: Graph, params: Params) -> int:
+    b = C.c_size_t()
+    _check(lib().hpmocd_workspace_size(graph.handle, C.byref(params), C.byref(b)),
+           "hpmocd_workspace_size")
+    return b.value
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _front_from(ptr) -> Front:
+    f = ptr.contents
+    k, n = f.n_solutions, f.n_nodes
+    out = Front(np.ctypeslib.as_array(f.labels, shape=(k, n)).copy(),
+                np.ctypeslib.as_array(f.intra_arcs, shape=(k,)).copy(),
+                np.ctypeslib.as_array(f.sum_deg_sq, shape=(k,)).copy(),
+                np.ctypeslib.as_array(f.f1, shape=(k,)).copy(),
+                np.ctypeslib.as_array(f.f2, shape=(k,)).copy(), f.selected)
+    lib().hpmocd_front_free(ptr)
+    return out
+
+
+def run(graph: Graph, params: Params | None = None, *, stream=None, workspace=None, flags=0,
+        profile: bool = False, on_generation=None, **kw):
+    """hpmocd_run / hpmocd_run_ex. Returns the Front, or (Front, profile dict) when
+    profile=True. ``on_generation(State)`` traces every generation (tests only)."""
+    import torch
+    if params is None:
+        params = make_params(**kw)
+    nbytes = workspace_size(graph, params)
+    ws = workspace if workspace is not None else torch.empty(nbytes, dtype=torch.uint8,
+                                                             device="cuda")
+    assert ws.numel() >= nbytes and ws.is_cuda
+    prof = Profile()
+    out = C.POINTER(_Front)()
+    cb = _TRACE()
+    if on_generation is not None:
+        def _cb(vp, _u):
+            v = vp.contents
+            np_, nn = v.pop_size, v.n_nodes
+            on_generation(State(
+                v.g, np.ctypeslib.as_array(v.labels, shape=(np_, nn)).copy(),
+                np.ctypeslib.as_array(v.A, shape=(np_,)).copy(),
+                np.ctypeslib.as_array(v.S, shape=(np_,)).copy(),
+                np.ctypeslib.as_array(v.f1, shape=(np_,)).copy(),
+                np.ctypeslib.as_array(v.f2, shape=(np_,)).copy(),
+                np.ctypeslib.as_array(v.rank, shape=(np_,)).copy() if v.rank else None,
+                np.ctypeslib.as_array(v.crowd, shape=(np_,)).copy() if v.crowd else None))
+        cb = _TRACE(_cb)
+    st = lib().hpmocd_run_ex(graph.handle, C.byref(params), C.c_void_p(ws.data_ptr()), nbytes,
+                             _stream_handle(stream), flags,
+                             C.byref(prof) if profile else None, cb, None, C.byref(out))
+    _check(st, "hpmocd_run_ex")
+    front = _front_from(out)
+    return (front, prof.as_dict()) if profile else front
+
+
+def evaluate(graph: Graph, labels, *, stream=None, timing=False):
+    """hpmocd_eval: objectives of n_ind partitions given as a CUDA int32 tensor (n_ind, n)."""
+    import torch
+    assert labels.is_cuda and labels.dtype == torch.int32 and labels.is_contiguous()
+    n_ind = labels.shape[0]
+    assert labels.shape[1] == graph.n
+    b = C.c_size_t()
+    _check(lib().hpmocd_eval_workspace_size(graph.handle, n_ind, C.byref(b)),
+           "hpmocd_eval_workspace_size")
+    ws = torch.empty(b.value, dtype=torch.uint8, device="cuda")
+    A = np.empty(n_ind, dtype=np.int64)
+    S = np.empty(n_ind, dtype=np.int64)
+    f1 = np.empty(n_ind, dtype=np.float64)
+    f2 = np.empty(n_ind, dtype=np.float64)
+    ms = C.c_double()
+    _check(lib().hpmocd_eval(graph.handle, C.c_void_p(labels.data_ptr()), n_ind,
+                             C.c_void_p(ws.data_ptr()), b.value, _stream_handle(stream),
+                             A.ctypes.data_as(C.POINTER(C.c_int64)),
+                             S.ctypes.data_as(C.POINTER(C.c_int64)),
+                             f1.ctypes.data_as(C.POINTER(C.c_double)),
+                             f2.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ms)),
+           "hpmocd_eval")
+    return (A, S, f1, f2, ms.value) if timing else (A, S, f1, f2)

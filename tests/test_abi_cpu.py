@@ -1,0 +1,99 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point its header declares,
+and its graph validation rejects what section 2.1 excludes before any device call."""
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2506_01752_amd as hp
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_entry_points():
+    text = open(os.path.join(ROOT, "include", "hpmocd.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hpmocd_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    declared = header_entry_points()
+    assert "hpmocd_run" in declared and "hpmocd_graph_create" in declared
+    out = subprocess.run(["nm", "-D", "--defined-only", hp.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\b(hpmocd_[a-z_]+)\b", out))
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    assert sorted(hp.EXPORTS) == declared
+    lib = hp.lib()
+    for s in declared:
+        assert hasattr(lib, s)
+
+
+def test_strerror_names_every_status():
+    for code, name in hp.ERR.items():
+        msg = hp.lib().hpmocd_strerror(code).decode()
+        assert msg and msg != "unknown status", (code, name)
+    assert hp.lib().hpmocd_strerror(0).decode() == "ok"
+
+
+def _csr(n, arcs):
+    arcs = sorted(arcs)
+    rp = np.zeros(n + 1, dtype=np.int32)
+    for u, _ in arcs:
+        rp[u + 1] += 1
+    rp = np.cumsum(rp).astype(np.int32)
+    col = np.array([v for _, v in arcs], dtype=np.int32)
+    return rp, col
+
+
+def test_validation_codes():
+    # asymmetric: arc 0->1 without 1->0
+    rp, col = _csr(3, [(0, 1), (1, 2), (2, 1)])
+    assert hp.graph_create_status(3, rp, col) == -2
+    # self-loop
+    rp, col = _csr(2, [(0, 0), (0, 1), (1, 0)])
+    assert hp.graph_create_status(2, rp, col) == -3
+    # duplicate edge
+    rp, col = _csr(2, [(0, 1), (0, 1), (1, 0), (1, 0)])
+    assert hp.graph_create_status(2, rp, col) == -4
+    # column out of range, negative column, non-monotone row_ptr, row_ptr[0] != 0
+    rp, col = _csr(2, [(0, 1), (1, 0)])
+    assert hp.graph_create_status(2, rp, np.array([5, 0], dtype=np.int32)) == -5
+    assert hp.graph_create_status(2, rp, np.array([-1, 0], dtype=np.int32)) == -5
+    assert hp.graph_create_status(2, np.array([0, 2, 1], dtype=np.int32),
+                                  np.array([1, 0], dtype=np.int32)) == -5
+    assert hp.graph_create_status(2, np.array([1, 1, 2], dtype=np.int32),
+                                  np.array([1, 0], dtype=np.int32)) == -5
+    # no edge (f1 = 0/0)
+    assert hp.graph_create_status(3, np.zeros(4, dtype=np.int32), np.zeros(0, dtype=np.int32)) == -6
+    # (2m)^2 > 2^53: the largest exact arc count is 94,906,265
+    assert hp.graph_create_status(1, np.array([0, 94906266], dtype=np.int32),
+                                  np.zeros(2, dtype=np.int32)) == -7
+    # bad arguments
+    assert hp.graph_create_status(0, np.zeros(1, dtype=np.int32), np.zeros(1, dtype=np.int32)) == -1
+
+
+def test_valid_graphs_pass_validation():
+    """A valid graph gets past validation: without a GPU the first device call fails
+    (ERR_HIP); with one the graph is created."""
+    for g in [synth.fig1_graph(), synth.appendix_graph(), synth.star(7),
+              synth.with_isolated(synth.path(5), 3)]:
+        st = hp.graph_create_status(g.n, g.row_ptr, g.col)
+        assert st in (0, -9), st
+    # unsorted adjacency is accepted (the library sorts it)
+    g = synth.fig3_graph()
+    col = g.col.copy()
+    for v in range(g.n):
+        col[g.row_ptr[v]:g.row_ptr[v + 1]] = col[g.row_ptr[v]:g.row_ptr[v + 1]][::-1]
+    assert hp.graph_create_status(g.n, g.row_ptr, col) in (0, -9)
+
+
+def test_no_cpu_fallback_when_library_missing(tmp_path, monkeypatch):
+    monkeypatch.setattr(hp, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(hp, "_lib", None)
+    with pytest.raises(RuntimeError):
+        hp.lib()

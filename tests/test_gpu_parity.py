@@ -1,0 +1,180 @@
+"""GPU path vs the CPU oracle, through the C ABI: bit-exact labels, integer counts and
+binary64 objectives (and, per generation, ranks and crowding distances)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2506_01752_amd as m
+    m.lib()
+    return m
+
+
+@pytest.fixture(scope="module")
+def stream(hp):
+    import torch
+    return torch.cuda.Stream()
+
+
+def bits(a):
+    return np.ascontiguousarray(a, dtype=np.float64).view(np.uint64)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def assert_front_equal(got, ref):
+    assert got.labels.shape == ref.labels.shape, (got.labels.shape, ref.labels.shape)
+    assert np.array_equal(got.labels, ref.labels)
+    assert np.array_equal(got.A, ref.A)
+    assert np.array_equal(got.S, ref.S)
+    assert np.array_equal(bits(got.f1), bits(ref.f1))
+    assert np.array_equal(bits(got.f2), bits(ref.f2))
+    assert got.selected == ref.selected
+
+
+def assert_states_equal(gs, os_):
+    assert len(gs) == len(os_)
+    for a, b in zip(gs, os_):
+        assert a.g == b.g
+        assert np.array_equal(a.labels, b.labels), f"labels differ at generation {a.g}"
+        assert np.array_equal(a.A, b.A) and np.array_equal(a.S, b.S), a.g
+        assert np.array_equal(bits(a.f1), bits(b.f1)) and np.array_equal(bits(a.f2), bits(b.f2))
+        if b.rank is None:
+            assert a.rank is None
+        else:
+            assert np.array_equal(a.rank, b.rank), a.g
+            assert np.array_equal(bits(a.crowd), bits(b.crowd)), a.g
+
+
+# ---------------------------------------------------------------------------------------
+# fitness kernel alone
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("gname", ["fig1", "appendix", "small_1k", "isolated", "star70"])
+@pytest.mark.parametrize("n_ind", [1, 3, 64, 100, 129, 300])
+def test_eval_matches_oracle(hp, stream, gname, n_ind):
+    import torch
+    g = {"fig1": synth.fig1_graph, "appendix": synth.appendix_graph, "small_1k": synth.small_1k,
+         "isolated": lambda: synth.with_isolated(synth.gnp(90, 0.08, 1), 13),
+         "star70": lambda: synth.star(70)}[gname]()
+    say(f"eval {gname} n={g.n} n_ind={n_ind}")
+    rng = np.random.default_rng(n_ind)
+    labs = []
+    for i in range(n_ind):
+        k = int(rng.integers(1, g.n + 1))
+        labs.append(rng.integers(0, k, size=g.n))
+    labs = np.stack(labs).astype(np.int32)
+    labs[0] = g.membership if g.membership is not None else labs[0]
+    dg = hp.Graph(g.row_ptr, g.col)
+    t = torch.from_numpy(labs).cuda()
+    A, S, f1, f2 = hp.evaluate(dg, t, stream=stream)
+    for i in range(n_ind):
+        ra, rs, r1, r2 = oracle.evaluate(g.row_ptr, g.col, labs[i])
+        assert (A[i], S[i]) == (ra, rs), i
+        assert bits([f1[i]])[0] == bits([r1])[0] and bits([f2[i]])[0] == bits([r2])[0]
+
+
+# ---------------------------------------------------------------------------------------
+# whole runs, traced every generation
+# ---------------------------------------------------------------------------------------
+def traced_pair(hp, stream, g, threads=1, **kw):
+    gs, os_ = [], []
+    dg = hp.Graph(g.row_ptr, g.col)
+    got = hp.run(dg, stream=stream, on_generation=gs.append, **kw)
+    ref = oracle.run(g.row_ptr, g.col, threads=threads, on_generation=os_.append, **kw)
+    return got, ref, gs, os_
+
+
+@pytest.mark.parametrize("gname", ["fig1", "fig3", "appendix", "star", "path", "k12",
+                                   "isolated", "two_cliques"])
+def test_run_small_graphs_every_generation(hp, stream, gname):
+    g = {"fig1": synth.fig1_graph, "fig3": synth.fig3_graph, "appendix": synth.appendix_graph,
+         "star": lambda: synth.star(40), "path": lambda: synth.path(33),
+         "k12": lambda: synth.complete(12),
+         "isolated": lambda: synth.with_isolated(synth.fig1_graph(), 7),
+         "two_cliques": lambda: synth.two_cliques(9, 40)}[gname]()
+    say(f"run {gname} n={g.n}")
+    got, ref, gs, os_ = traced_pair(hp, stream, g, pop_size=24, generations=15, seed=3)
+    assert_states_equal(gs, os_)
+    assert_front_equal(got, ref)
+
+
+@pytest.mark.parametrize("pop,es,cp,mp,T", [(1, 4, 0.9, 0.1, 3), (2, 1, 0.9, 0.1, 4),
+                                            (3, 2, 1.0, 1.0, 4), (100, 3, 0.0, 0.5, 3),
+                                            (17, 8, 1.0, 0.0, 5), (64, 4, 0.8, 0.2, 0),
+                                            (130, 5, 0.7, 0.3, 3), (512, 4, 0.9, 0.1, 2)])
+def test_run_parameter_edges(hp, stream, pop, es, cp, mp, T):
+    g = synth.small_1k(seed=2)
+    say(f"params pop={pop} es={es} cp={cp} mp={mp} T={T}")
+    got, ref, gs, os_ = traced_pair(hp, stream, g, threads=4, pop_size=pop, generations=T,
+                                    crossover_p=cp, mutation_p=mp, parents_per_child=es,
+                                    seed=11)
+    assert_states_equal(gs, os_)
+    assert_front_equal(got, ref)
+
+
+def test_run_1k_full_every_generation(hp, stream):
+    """|V| = 1,000 planted partition, pop 100, 100 generations: every generation."""
+    g = synth.small_1k()
+    say("run small_1k pop100 T100 traced")
+    got, ref, gs, os_ = traced_pair(hp, stream, g, threads=4, **synth.GA_DEFAULT)
+    assert_states_equal(gs, os_)
+    assert_front_equal(got, ref)
+
+
+def test_graph_replay_equals_plain_launches(hp, stream):
+    g = synth.small_1k(seed=5)
+    dg = hp.Graph(g.row_ptr, g.col)
+    kw = dict(pop_size=50, generations=9, seed=9)
+    say("graph replay vs plain")
+    a = hp.run(dg, stream=stream, **kw)                       # hipGraph replay of the loop
+    b = hp.run(dg, stream=stream, flags=hp.NO_GRAPH, **kw)    # one launch per kernel
+    c = hp.run(dg, stream=stream, flags=hp.TIME_KERNELS, profile=True, **kw)[0]
+    ref = oracle.run(g.row_ptr, g.col, **kw)
+    for x in (a, b, c):
+        assert_front_equal(x, ref)
+
+
+def test_high_degree_mutation_paths(hp, stream):
+    """Hubs above the per-lane limit (32), and above the LDS sort capacity (4096)."""
+    rng = np.random.default_rng(0)
+    hub_edges = [(0, i) for i in range(1, 5001)] + [(1, i) for i in range(2, 200)]
+    extra = rng.integers(0, 5001, size=(6000, 2))
+    g = synth.csr_from_edges(5001, np.concatenate([np.array(hub_edges), extra]))
+    say(f"hubs n={g.n} maxdeg={np.diff(g.row_ptr).max()}")
+    got, ref, gs, os_ = traced_pair(hp, stream, g, threads=4, pop_size=20, generations=4,
+                                    mutation_p=0.6, seed=5)
+    assert_states_equal(gs, os_)
+    assert_front_equal(got, ref)
+
+
+@pytest.mark.parametrize("mu", [0.1, 0.7])
+def test_run_40k_traced(hp, stream, mu):
+    """|V| = 40,000 planted partition (the paper's mid scale), pop 100, first generations."""
+    g = synth.mid_40k(mu)
+    say(f"run mid_40k mu={mu}")
+    kw = dict(synth.GA_DEFAULT, generations=4)
+    got, ref, gs, os_ = traced_pair(hp, stream, g, threads=8, **kw)
+    assert_states_equal(gs, os_)
+    assert_front_equal(got, ref)
+
+
+def test_deterministic_repeat(hp, stream):
+    g = synth.small_1k(seed=7)
+    dg = hp.Graph(g.row_ptr, g.col)
+    a = hp.run(dg, stream=stream, pop_size=40, generations=12, seed=1)
+    b = hp.run(dg, stream=stream, pop_size=40, generations=12, seed=1)
+    assert_front_equal(a, b)
