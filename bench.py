@@ -1,0 +1,171 @@
+"""Benchmark of the HP-MOCD hot path on one MI355X.
+
+One step = one whole run of the method (initialisation, T generations of tournament ->
+crossover -> mutation -> fitness -> environmental selection, front extraction) on a
+synthetic planted-partition graph already resident in HBM. The reported value is the
+fitness throughput in edge-evaluations per second (one undirected edge tested for one
+individual; one individual evaluation = m edge-evaluations), from HIP events recorded by the
+library around every fitness launch on the run's stream; generations per second come from
+events around the generation loop.
+
+Prints one JSON line. ``--gpus N`` with N > 1 is refused: this build targets one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fitness edge-evals/s & gens/s at 1M nodes; batched runs/s + p50/p99 latency"
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD public specification
+
+WORKLOADS = {
+    "planted_partition_1M": ("large_1m", {}),
+    "planted_partition_40k_mu0.3": ("mid_40k", {"mu": 0.3}),
+    "planted_partition_1k": ("small_1k", {}),
+}
+
+
+def fitness_bytes(n: int, m2: int, pop: int) -> int:
+    """Algorithmic HBM bytes of one fitness launch over a population of `pop` individuals
+    stored node-major: the CSR once (row_ptr + col) and every individual's label row once,
+    plus the per-individual counters written. Histogram traffic is scratch, not counted."""
+    return 4 * (n + 1) + 4 * m2 + 4 * n * pop + 16 * pop
+
+
+def per_individual_bytes(n: int, m2: int) -> int:
+    """Bytes one individual evaluation reads if evaluated alone: CSR + its label row."""
+    return 4 * (n + 1) + 4 * m2 + 4 * n
+
+
+def cpu_baseline(g, seed: int, target_s: float = 15.0):
+    """The oracle's evaluation, single-threaded, on a bounded sample of individuals of the
+    same workload (the initial population's first rows)."""
+    import numpy as np
+
+    import oracle
+    oracle.build()
+    first = oracle.init_individual(g.row_ptr, g.col, seed, 0)[None, :]
+    t0 = time.perf_counter()
+    oracle.evaluate_batch(g.row_ptr, g.col, first)
+    t1 = time.perf_counter()
+    oracle.evaluate_batch(g.row_ptr, g.col, np.repeat(first, 3, axis=0))
+    one = max((time.perf_counter() - t1) - (t1 - t0), 1e-6) / 2   # per evaluation, graph copy excluded
+    k = int(min(100, max(3, target_s / one)))
+    labs = np.stack([oracle.init_individual(g.row_ptr, g.col, seed, i) for i in range(k)])
+    t0 = time.perf_counter()
+    oracle.evaluate_batch(g.row_ptr, g.col, labs)
+    dt = time.perf_counter() - t0
+    return {"value": k * g.m / dt, "unit": "edge-evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} individual evaluations (initial-population rows) of the same graph, "
+                      f"serial C oracle, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="planted_partition_1M", choices=sorted(WORKLOADS))
+    ap.add_argument("--generations", type=int, default=100)
+    ap.add_argument("--pop", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--graph-mode", action="store_true",
+                    help="also time runs whose generation loop is replayed from a hipGraph")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2506_01752_amd as hp
+    import synth
+
+    maker, extra = WORKLOADS[args.workload]
+    g = getattr(synth, maker)(**extra)
+    kw = dict(synth.GA_DEFAULT, pop_size=args.pop, generations=args.generations)
+    params = hp.make_params(**kw)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    dg = hp.Graph(g.row_ptr, g.col)
+    ws = torch.empty(hp.workspace_size(dg, params), dtype=torch.uint8, device="cuda")
+    print(f"# workload {args.workload}: n={g.n} m={g.m} pop={args.pop} T={args.generations}",
+          file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        hp.run(dg, params, stream=stream, workspace=ws, flags=hp.TIME_KERNELS, profile=True)
+    torch.cuda.synchronize()
+    profs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, prof = hp.run(dg, params, stream=stream, workspace=ws, flags=hp.TIME_KERNELS,
+                         profile=True)
+        profs.append(prof)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print(f"# timed {args.steps} runs in {wall:.3f} s", file=sys.stderr, flush=True)
+
+    T, pop = args.generations, args.pop
+    launches = sum(p["fitness_launches"] for p in profs)
+    fit_ms = sum(p["fitness_ms"] for p in profs)
+    sweep_ms = sum(p["sweep_ms"] for p in profs)
+    loop_ms = sum(p["loop_ms"] for p in profs)
+    evals = sum(p["individual_evals"] for p in profs)
+    edge_evals = evals * g.m
+    value = edge_evals / ((fit_ms + sweep_ms) / 1e3)
+    scan_ms = fit_ms / launches
+    bytes_launch = fitness_bytes(g.n, 2 * g.m, pop)
+    achieved = bytes_launch / (scan_ms / 1e3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edge-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": g.n, "m": g.m,
+                   "mean_deg": g.info.get("mean_deg"), "mu": g.info.get("mu"),
+                   "max_deg": g.info.get("realised_max_deg"), "pop_size": pop,
+                   "generations": T, "crossover_p": kw["crossover_p"],
+                   "mutation_p": kw["mutation_p"], "parents_per_child": kw["parents_per_child"],
+                   "seed": kw["seed"], "graph_seed": 0},
+        "gens_per_s": T * args.steps / (loop_ms / 1e3) if T else None,
+        "fitness_scan_ms_per_launch": scan_ms,
+        "fitness_sweep_ms_per_launch": sweep_ms / launches,
+        "variation_ms_per_gen": sum(p["variation_ms"] for p in profs) / max(1, T * args.steps),
+        "select_ms_per_gen": sum(p["select_ms"] for p in profs) / max(1, T * args.steps),
+        "per_individual_equiv_GBps": pop * per_individual_bytes(g.n, 2 * g.m) / (scan_ms / 1e3) / 1e9,
+        "roofline": {"bound": "hbm", "kernel": "k_fitness", "achieved": achieved,
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": None},
+    }
+    if args.graph_mode and T >= 2:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        loops = []
+        for _ in range(args.steps):
+            _, p = hp.run(dg, params, stream=stream, workspace=ws, profile=True)
+            loops.append(p["loop_ms"])
+        torch.cuda.synchronize()
+        out["graph_mode"] = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / args.steps,
+                             "gens_per_s": T * args.steps / (sum(loops) / 1e3)}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, kw["seed"])
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -64,6 +64,8 @@ def _L():
         lib.or_thr.argtypes = [C.c_double]
         lib.or_thr.restype = C.c_uint64
         lib.or_eval.argtypes = [C.c_int32, i32p, i32p, i32p, i64p, i64p, f64p, f64p]
+        lib.or_eval_batch.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_int32, i64p, i64p, f64p,
+                                      f64p]
         lib.or_init_individual.argtypes = [C.c_int32, i32p, i32p, C.c_uint64, C.c_int32, i32p]
         lib.or_crossover.argtypes = [C.c_int32, C.c_int32, i32p, C.c_int32, C.c_uint64,
                                      C.c_uint32, C.c_uint32, i32p]
@@ -113,6 +115,19 @@ def evaluate(row_ptr, col, labels):
     _L().or_eval(len(rp) - 1, _p(rp, C.c_int32), _p(cl, C.c_int32), _p(lb, C.c_int32),
                  C.byref(A), C.byref(S), C.byref(f1), C.byref(f2))
     return A.value, S.value, f1.value, f2.value
+
+
+def evaluate_batch(row_ptr, col, labels):
+    """evaluate() of every row of labels (k x n) against one copy of the graph."""
+    rp, cl, lb = _i32(row_ptr), _i32(col), _i32(labels)
+    k = lb.shape[0]
+    A = np.empty(k, dtype=np.int64)
+    S = np.empty(k, dtype=np.int64)
+    f1 = np.empty(k, dtype=np.float64)
+    f2 = np.empty(k, dtype=np.float64)
+    _L().or_eval_batch(len(rp) - 1, _p(rp, C.c_int32), _p(cl, C.c_int32), _p(lb, C.c_int32), k,
+                       _p(A, C.c_int64), _p(S, C.c_int64), _p(f1, C.c_double), _p(f2, C.c_double))
+    return A, S, f1, f2
 
 
 def init_individual(row_ptr, col, seed: int, i: int) -> np.ndarray:

@@ -153,6 +153,19 @@ void or_eval(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_
     graph_free(&g);
 }
 
+/* k partitions (k x n, row-major) against one copy of the graph */
+void or_eval_batch(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *lab,
+                   int32_t k, int64_t *A, int64_t *S, double *f1, double *f2)
+{
+    or_graph g;
+    graph_copy(&g, n, row_ptr, col);
+    int64_t *D = (int64_t *)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    for (int32_t i = 0; i < k; ++i)
+        eval_graph(&g, lab + (size_t)i * (size_t)n, D, A + i, S + i, f1 + i, f2 + i);
+    free(D);
+    graph_free(&g);
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* Plurality with a random tie-break (eq. "arg_max"): among vals[0..k), take the labels of */
 /* maximal multiplicity, in ascending order, and return the one at index pick(r, #ties).   */

@@ -438,6 +438,18 @@ int hpmocd_run_ex(const hpmocd_graph *G, const hpmocd_params *p, void *ws, size_
     EventSet evs;
     hipEvent_t e_start = nullptr, e_loop0 = nullptr, e_loop1 = nullptr, e_end = nullptr;
     hipEvent_t e_fit0 = nullptr, e_fit1 = nullptr, e_sw1 = nullptr;
+    // kernel-group events for every generation are created before the run starts, and read
+    // only after it ends, so timing adds no host synchronisation to the loop
+    std::vector<std::vector<EventPair>> gen_events;
+    if (time_kernels) {
+        gen_events.assign((size_t)T, std::vector<EventPair>(5));
+        for (auto &v : gen_events)
+            for (auto &pr : v) {
+                pr.a = evs.make();
+                pr.b = evs.make();
+                if (!pr.a || !pr.b) return HPMOCD_ERR_HIP;
+            }
+    }
     if (prof) {
         e_start = evs.make();
         e_loop0 = evs.make();
@@ -489,25 +501,10 @@ int hpmocd_run_ex(const hpmocd_graph *G, const hpmocd_params *p, void *ws, size_
         gdone = (T / 2) * 2;
         cur = 0;
     }
-    std::vector<EventPair> ev;
     for (int32_t gen = gdone + 1; gen <= T; ++gen) {
-        if (time_kernels) {
-            ev.assign(5, EventPair{});
-            for (auto &pr : ev) {
-                pr.a = evs.make();
-                pr.b = evs.make();
-                if (!pr.a || !pr.b) return HPMOCD_ERR_HIP;
-            }
-        }
-        HIP_TRY(generation(dg, c, L, cur, s, time_kernels ? &ev : nullptr));
+        std::vector<EventPair> *ev = time_kernels ? &gen_events[(size_t)(gen - 1)] : nullptr;
+        HIP_TRY(generation(dg, c, L, cur, s, ev));
         cur = 1 - cur;
-        if (time_kernels) {
-            HIP_TRY(hipEventSynchronize(ev[4].b));
-            sel_ms += elapsed(ev[0].a, ev[0].b) + elapsed(ev[4].a, ev[4].b);
-            var_ms += elapsed(ev[1].a, ev[1].b);
-            fit_ms += elapsed(ev[2].a, ev[2].b);
-            sweep_ms += elapsed(ev[3].a, ev[3].b);
-        }
         if (trace && (rc = emit_state(G, c, L, cur, gen, s, trace, user))) return rc;
     }
     if (prof) HIP_TRY(hipEventRecord(e_loop1, s));
@@ -554,6 +551,14 @@ int hpmocd_run_ex(const hpmocd_graph *G, const hpmocd_params *p, void *ws, size_
         }
     }
     f->selected = sel;
+    if (time_kernels) {
+        for (auto &ev : gen_events) {
+            sel_ms += elapsed(ev[0].a, ev[0].b) + elapsed(ev[4].a, ev[4].b);
+            var_ms += elapsed(ev[1].a, ev[1].b);
+            fit_ms += elapsed(ev[2].a, ev[2].b);
+            sweep_ms += elapsed(ev[3].a, ev[3].b);
+        }
+    }
     if (prof) {
         prof->total_ms = elapsed(e_start, e_end);
         prof->loop_ms = elapsed(e_loop0, e_loop1);
