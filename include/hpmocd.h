@@ -94,7 +94,7 @@ typedef struct {
     double total_ms;           /* init through front extraction */
     double loop_ms;            /* generations 1..T */
     double fitness_ms;         /* edge-scan fitness kernels (all launches) */
-    double sweep_ms;           /* community-degree square-sum kernels */
+    double sweep_ms;           /* clearing the community-degree histogram after each scan */
     double variation_ms;       /* crossover + mutation kernels */
     double select_ms;          /* ranking / crowding / selection kernels */
     int64_t fitness_launches;  /* number of edge-scan launches */

@@ -22,6 +22,8 @@ struct hpmocd_graph {
     int device = 0;
     int32_t *d_rp = nullptr, *d_col = nullptr, *d_small = nullptr, *d_large = nullptr;
     int32_t n_small = 0, n_large = 0;
+    int32_t class_end[N_DEG_CLASSES] = {0, 0, 0, 0, 0, 0};
+    int32_t large_max_deg = 0;
 };
 
 namespace {
@@ -49,6 +51,8 @@ DevGraph dev_graph(const hpmocd_graph *g)
     d.n_small = g->n_small;
     d.large_nodes = g->d_large;
     d.n_large = g->n_large;
+    for (int k = 0; k < N_DEG_CLASSES; ++k) d.class_end[k] = g->class_end[k];
+    d.large_max_deg = g->large_max_deg;
     return d;
 }
 
@@ -90,14 +94,17 @@ struct RunLayout {
     int32_t *pool[2] = {nullptr, nullptr};
     int32_t *q[2] = {nullptr, nullptr};
     int32_t *C = nullptr;
-    int32_t *D = nullptr;
+    int32_t *D = nullptr;       // plain histogram (only when the binned one does not apply)
+    HistPlan hp;
+    uint32_t *run = nullptr, *off = nullptr;  // binned histogram work areas
     DevState st{};
     size_t bytes = 0;
 };
 
-RunLayout carve_run(void *ws, int32_t n, int32_t pop, int32_t es)
+RunLayout carve_run(void *ws, int32_t n, int32_t pop, int32_t es, int32_t max_deg)
 {
     RunLayout L;
+    L.hp = hist_plan(n, pop, max_deg);
     L.ld = round16(pop);
     L.plane = (size_t)n * (size_t)L.ld * sizeof(int32_t);
     Carver cv(ws);
@@ -107,7 +114,12 @@ RunLayout carve_run(void *ws, int32_t n, int32_t pop, int32_t es)
     L.q[0] = cv.take<int32_t>(cells);
     L.q[1] = cv.take<int32_t>(cells);
     L.C = cv.take<int32_t>(cells);
-    L.D = cv.take<int32_t>(cells);
+    if (L.hp.enabled) {
+        L.run = cv.take<uint32_t>(L.hp.entries);
+        L.off = cv.take<uint32_t>(L.hp.offsets);
+    } else {
+        L.D = cv.take<int32_t>(cells);
+    }
     DevState &s = L.st;
     s.gen = cv.take<int32_t>(1);
     s.ps_id = cv.take<int32_t>(pop);
@@ -176,10 +188,12 @@ hipError_t generation(const DevGraph &g, const GaConst &c, const RunLayout &L, i
     if ((e = launch_mutation(g, c, L.st, L.C, L.q[nxt], s)) != hipSuccess) return e;
     mark(1, true);
     mark(2, false);
-    if ((e = launch_fitness(g, L.q[nxt], c.ld, c.pop, L.D, L.st.Aq, s)) != hipSuccess) return e;
+    if ((e = launch_fitness(g, L.q[nxt], c.ld, c.pop, L.hp, L.run, L.off, L.D, L.st.Aq, L.st.Sq,
+                            s)) != hipSuccess)
+        return e;
     mark(2, true);
     mark(3, false);
-    if ((e = launch_sweep(g.n, nullptr, c.ld, c.pop, L.D, L.st.Sq, s)) != hipSuccess) return e;
+    if (!L.hp.enabled && (e = launch_fill_zero(L.D, L.plane, s)) != hipSuccess) return e;
     mark(3, true);
     mark(4, false);
     if ((e = launch_select(c, g.m2, L.st, s)) != hipSuccess) return e;
@@ -257,19 +271,27 @@ namespace {
 struct EvalLayout {
     int32_t ld = 0;
     size_t plane = 0;
+    HistPlan hp;
+    uint32_t *run = nullptr, *off = nullptr;
     int32_t *lab = nullptr, *D = nullptr;
     unsigned long long *A = nullptr, *S = nullptr;
     double *f1 = nullptr, *f2 = nullptr;
     size_t bytes = 0;
 };
-EvalLayout carve_eval(void *ws, int32_t n, int32_t n_ind)
+EvalLayout carve_eval(void *ws, int32_t n, int32_t n_ind, int32_t max_deg)
 {
     EvalLayout L;
     L.ld = round16(n_ind);
     L.plane = (size_t)n * (size_t)L.ld * sizeof(int32_t);
+    L.hp = hist_plan(n, n_ind, max_deg);
     Carver cv(ws);
     L.lab = cv.take<int32_t>((size_t)n * L.ld);
-    L.D = cv.take<int32_t>((size_t)n * L.ld);
+    if (L.hp.enabled) {
+        L.run = cv.take<uint32_t>(L.hp.entries);
+        L.off = cv.take<uint32_t>(L.hp.offsets);
+    } else {
+        L.D = cv.take<int32_t>((size_t)n * L.ld);
+    }
     L.A = cv.take<unsigned long long>(n_ind);
     L.S = cv.take<unsigned long long>(n_ind);
     L.f1 = cv.take<double>(n_ind);
@@ -359,6 +381,13 @@ int hpmocd_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *col,
     g->max_deg = max_deg;
     g->n_small = (int32_t)small.size();
     g->n_large = (int32_t)large.size();
+    for (int k = 0; k < N_DEG_CLASSES; ++k) {
+        int32_t e = 0;
+        for (int32_t v : small)
+            if (row_ptr[v + 1] - row_ptr[v] <= DEG_CLASS_MAX[k]) ++e;
+        g->class_end[k] = e;
+    }
+    g->large_max_deg = large.empty() ? 0 : row_ptr[large[0] + 1] - row_ptr[large[0]];
     bool ok = hipGetDevice(&g->device) == hipSuccess;
     ok = ok && hipMalloc(&g->d_rp, sizeof(int32_t) * ((size_t)n + 1)) == hipSuccess;
     ok = ok && hipMalloc(&g->d_col, sizeof(int32_t) * (size_t)m2) == hipSuccess;
@@ -402,7 +431,7 @@ int hpmocd_workspace_size(const hpmocd_graph *g, const hpmocd_params *p, size_t 
     if (!g || !bytes) return HPMOCD_ERR_ARG;
     int rc = check_params(p);
     if (rc) return rc;
-    *bytes = carve_run(nullptr, g->n, p->pop_size, p->parents_per_child).bytes;
+    *bytes = carve_run(nullptr, g->n, p->pop_size, p->parents_per_child, g->max_deg).bytes;
     return HPMOCD_OK;
 }
 
@@ -426,7 +455,7 @@ int hpmocd_run_ex(const hpmocd_graph *G, const hpmocd_params *p, void *ws, size_
     if (rc) return rc;
     if ((rc = check_device(G))) return rc;
     const int32_t pop = p->pop_size, T = p->generations, n = G->n;
-    RunLayout L = carve_run(ws, n, pop, p->parents_per_child);
+    RunLayout L = carve_run(ws, n, pop, p->parents_per_child, G->max_deg);
     if (ws_bytes < L.bytes) return HPMOCD_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     const DevGraph dg = dev_graph(G);
@@ -464,14 +493,14 @@ int hpmocd_run_ex(const hpmocd_graph *G, const hpmocd_params *p, void *ws, size_
     }
 
     // initial population (Alg. 1 phases 1-2) into offspring buffer 0
-    HIP_TRY(launch_fill_zero(L.D, L.plane, s));
+    if (!L.hp.enabled) HIP_TRY(launch_fill_zero(L.D, L.plane, s));
     HIP_TRY(launch_fill_zero(L.st.Aq, sizeof(unsigned long long) * pop, s));
     HIP_TRY(launch_fill_zero(L.st.Sq, sizeof(unsigned long long) * pop, s));
     HIP_TRY(launch_init(dg, c, L.q[0], s));
     if (prof) HIP_TRY(hipEventRecord(e_fit0, s));
-    HIP_TRY(launch_fitness(dg, L.q[0], c.ld, pop, L.D, L.st.Aq, s));
+    HIP_TRY(launch_fitness(dg, L.q[0], c.ld, pop, L.hp, L.run, L.off, L.D, L.st.Aq, L.st.Sq, s));
     if (prof) HIP_TRY(hipEventRecord(e_fit1, s));
-    HIP_TRY(launch_sweep(n, nullptr, c.ld, pop, L.D, L.st.Sq, s));
+    if (!L.hp.enabled) HIP_TRY(launch_fill_zero(L.D, L.plane, s));
     if (prof) HIP_TRY(hipEventRecord(e_sw1, s));
     HIP_TRY(launch_init_state(c, G->m2, L.st, s));
     int cur = 0;
@@ -583,7 +612,7 @@ int hpmocd_run(const hpmocd_graph *g, const hpmocd_params *p, void *ws, size_t w
 int hpmocd_eval_workspace_size(const hpmocd_graph *g, int32_t n_ind, size_t *bytes)
 {
     if (!g || !bytes || n_ind < 1) return HPMOCD_ERR_ARG;
-    *bytes = carve_eval(nullptr, g->n, n_ind).bytes;
+    *bytes = carve_eval(nullptr, g->n, n_ind, g->max_deg).bytes;
     return HPMOCD_OK;
 }
 
@@ -594,11 +623,11 @@ int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, v
     if (!G || !d_labels || n_ind < 1 || !ws || !A || !S || !f1 || !f2) return HPMOCD_ERR_ARG;
     int rc = check_device(G);
     if (rc) return rc;
-    EvalLayout L = carve_eval(ws, G->n, n_ind);
+    EvalLayout L = carve_eval(ws, G->n, n_ind, G->max_deg);
     if (ws_bytes < L.bytes) return HPMOCD_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
     const DevGraph dg = dev_graph(G);
-    HIP_TRY(launch_fill_zero(L.D, L.plane, s));
+    if (!L.hp.enabled) HIP_TRY(launch_fill_zero(L.D, L.plane, s));
     HIP_TRY(launch_fill_zero(L.A, sizeof(unsigned long long) * n_ind, s));
     HIP_TRY(launch_fill_zero(L.S, sizeof(unsigned long long) * n_ind, s));
     HIP_TRY(launch_transpose_in(d_labels, G->n, n_ind, L.ld, L.lab, s));
@@ -610,8 +639,7 @@ int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, v
         if (!a || !b) return HPMOCD_ERR_HIP;
         HIP_TRY(hipEventRecord(a, s));
     }
-    HIP_TRY(launch_fitness(dg, L.lab, L.ld, n_ind, L.D, L.A, s));
-    HIP_TRY(launch_sweep(G->n, nullptr, L.ld, n_ind, L.D, L.S, s));
+    HIP_TRY(launch_fitness(dg, L.lab, L.ld, n_ind, L.hp, L.run, L.off, L.D, L.A, L.S, s));
     if (kernel_ms) HIP_TRY(hipEventRecord(b, s));
     HIP_TRY(launch_finalize(G->m2, n_ind, L.A, L.S, L.f1, L.f2, s));
     std::vector<unsigned long long> hA(n_ind), hS(n_ind);

@@ -20,8 +20,14 @@ namespace hpm {
 constexpr int HPMOCD_MAX_PARENTS_DEV = HPMOCD_MAX_PARENTS;
 constexpr int HPMOCD_MAX_POP_DEV = HPMOCD_MAX_POP;
 
-constexpr int SMALL_DEG_MAX = 32;   // mutation of nodes up to this degree: one lane per node
-constexpr int LARGE_SORT_CAP = 4096;  // larger nodes: LDS sort up to this degree, then a scan
+// Mutation work classes by degree (upper bounds). Degrees 1..32: one (node, offspring) item
+// per lane, neighbour labels sorted in registers. Degrees 33..512: one item per wave, the
+// labels spread 1, 2, 4 or 8 per lane and sorted across the wave. Higher degrees: one item
+// per wave with an LDS sort (up to LARGE_SORT_CAP neighbours) or, above that, an exact scan.
+constexpr int N_DEG_CLASSES = 6;
+constexpr int DEG_CLASS_MAX[N_DEG_CLASSES] = {16, 32, 64, 128, 256, 512};
+constexpr int SMALL_DEG_MAX = 512;
+constexpr int LARGE_SORT_CAP = 2048;
 constexpr int SEL_THREADS = 1024;   // selection kernels: one workgroup, one thread per point
 
 struct DevGraph {
@@ -31,8 +37,10 @@ struct DevGraph {
     const int32_t *col;
     const int32_t *small_nodes;  // nodes with 1 <= deg <= SMALL_DEG_MAX, ascending degree
     int32_t n_small;
+    int32_t class_end[N_DEG_CLASSES];  // end of each degree class within small_nodes
     const int32_t *large_nodes;  // nodes with deg > SMALL_DEG_MAX, descending degree
     int32_t n_large;
+    int32_t large_max_deg;       // largest degree (0 when there is no large node)
 };
 
 // Generation state kept on the device (small arrays; the populations are passed apart).
@@ -69,10 +77,29 @@ struct GaConst {
 // ---- launchers (kernels.hip) -----------------------------------------------------------
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 hipError_t launch_init(const DevGraph &g, const GaConst &c, int32_t *Q, hipStream_t s);
+// Plan of the binned community-degree histogram (see kernels.hip): labels are split into
+// tiles of 2^rbits values; pass 1 bins every (label, degree) pair of a chunk of nb nodes and
+// a group of 16 individuals into runs per (tile, individual); pass 2 builds each tile's
+// histogram in LDS. Used when every degree fits the entry's 32 - rbits bits and nb >= 64.
+constexpr int HB_CG = 16;  // individuals per bin group
+struct HistPlan {
+    int32_t rbits = 0;     // tile = 2^rbits label values
+    int32_t tiles = 0;     // T = ceil(n / 2^rbits)
+    int32_t nb = 0;        // nodes per pass-1 chunk
+    int32_t nchunks = 0, ngroups = 0;
+    bool enabled = false;
+    size_t entries = 0;    // uint32 entries of the run area
+    size_t offsets = 0;    // uint32 offsets (per chunk and group: tiles * 16 + 1)
+};
+HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg);
+
+// A and S of every individual of a node-major population.
+//  binned (plan.enabled): run/off are work areas of plan.entries / plan.offsets words;
+//  otherwise: D must be all zero on entry and is left holding the community degree sums
+//  (clear it before the next call).
 hipError_t launch_fitness(const DevGraph &g, const int32_t *lab, int32_t ld, int32_t pop,
-                          int32_t *D, unsigned long long *A, hipStream_t s);
-hipError_t launch_sweep(int32_t n, const int32_t *lab_unused, int32_t ld, int32_t pop,
-                        int32_t *D, unsigned long long *S, hipStream_t s);
+                          const HistPlan &plan, uint32_t *run, uint32_t *off, int32_t *D,
+                          unsigned long long *A, unsigned long long *S, hipStream_t s);
 hipError_t launch_init_state(const GaConst &c, int64_t m2, const DevState &st, hipStream_t s);
 hipError_t launch_rank_parents(const GaConst &c, int64_t m2, const DevState &st,
                                hipStream_t s);

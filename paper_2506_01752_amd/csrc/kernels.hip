@@ -101,7 +101,7 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
 // initialisation (Alg. 1 InitializePopulation): node v of individual j takes its own id or
 // the id of a uniformly drawn neighbour (sorted adjacency), one Philox block per (v, j).
 // ---------------------------------------------------------------------------------------
-constexpr int NODE_BLOCK = 32;  // nodes per workgroup in the per-(node, individual) kernels
+constexpr int NODE_BLOCK = 32;  // nodes per workgroup in the init kernel
 
 __global__ __launch_bounds__(256) void k_init(DevGraph g, GaConst c, int32_t *__restrict__ Q,
                                               FastDiv divpop)
@@ -133,116 +133,310 @@ hipError_t launch_init(const DevGraph &g, const GaConst &c, int32_t *Q, hipStrea
 // lanes hold two individuals each (columns 2l, 2l+1 of a 128-column chunk). For every arc
 // (v,u) the wave reads the node-major row of u once (a contiguous 8-byte-per-lane load),
 // compares with v's row and counts intra arcs per lane. v, its arc range and the neighbour
-// ids are wave-uniform (scalar loads). D[label][col] += deg(v) by device-scope atomics.
+// ids are wave-uniform (scalar loads); arcs go eight at a time, all eight loads in flight.
+// Community degree sums: D[label][col] += deg(v) by device-scope atomics whose returned
+// old value gives S exactly, since sum over the additions of (old + d)^2 - old^2 telescopes
+// to sum_c D_c^2 whatever order the atomics take.
 // ---------------------------------------------------------------------------------------
-constexpr int FIT_NODES_PER_WAVE = 32;
-constexpr int FIT_UNROLL = 8;
+constexpr int FIT_ARCS = 16;   // arcs in flight per wave in the scan phase
+constexpr int FIT_NODES = 8;   // nodes per batch in the histogram phase
 
+__device__ __forceinline__ unsigned long long sq_step(int old, int d)
+{
+    return 2ull * (unsigned long long)(unsigned)old * (unsigned)d +
+           (unsigned long long)(unsigned)d * (unsigned)d;
+}
+
+// Phase 1 walks the wave's arc range [row_ptr[v0], row_ptr[v1]) as one flat stream, 16 arcs
+// at a time: for each arc (s,u) it loads the rows of u and of its source s (the source row
+// is re-read from L1) and counts equal labels. Phase 2 then adds deg(v) into the histogram
+// for 8 nodes at a time. Keeping the histogram atomics out of phase 1 matters: vector
+// memory counters drain in order, so an atomic issued between two gathers would make the
+// second wait for the atomic's round trip.
 __global__ __launch_bounds__(256) void k_fitness(DevGraph g, const int32_t *__restrict__ lab,
                                                  int32_t ld, int32_t pop, int32_t nchunks,
-                                                 int32_t *__restrict__ D,
-                                                 unsigned long long *__restrict__ A)
+                                                 int32_t npw, int32_t *__restrict__ D,
+                                                 unsigned long long *__restrict__ A,
+                                                 unsigned long long *__restrict__ S,
+                                                 int32_t atomics_phase)
 {
     const int lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
     const int chunk = wave % nchunks;
-    const int64_t v0 = (int64_t)(wave / nchunks) * FIT_NODES_PER_WAVE;
+    const int32_t v0 = (int32_t)min((int64_t)(wave / nchunks) * npw, (int64_t)g.n);
     if (v0 >= g.n) return;
-    const int64_t v1 = min(v0 + FIT_NODES_PER_WAVE, (int64_t)g.n);
+    const int32_t v1 = (int32_t)min((int64_t)v0 + npw, (int64_t)g.n);
     const int c0 = chunk * 128 + 2 * lane;
-    const bool act0 = c0 < pop, act1 = c0 + 1 < pop;
+    const bool act1 = c0 + 1 < pop;
+    if (c0 >= pop) return;
+    const int32_t *__restrict__ lc = lab + c0;
+
+    // phase 1: intra-community arcs
     int cnt0 = 0, cnt1 = 0;
-    if (act0) {
-        for (int64_t v = v0; v < v1; ++v) {
-            const int32_t rs = g.row_ptr[v], re = g.row_ptr[v + 1];
-            const int2 own = *(const int2 *)(lab + (size_t)v * ld + c0);
-            int32_t e = rs;
-            for (; e + FIT_UNROLL <= re; e += FIT_UNROLL) {
-                int32_t u[FIT_UNROLL];
+    const int32_t a0 = g.row_ptr[v0], a1 = g.row_ptr[v1];
+    int32_t src = v0, src_end = g.row_ptr[v0 + 1];
+    for (int32_t e = a0; e < a1; e += FIT_ARCS) {
+        int32_t u[FIT_ARCS], sv[FIT_ARCS];
 #pragma unroll
-                for (int k = 0; k < FIT_UNROLL; ++k) u[k] = g.col[e + k];
-                int2 x[FIT_UNROLL];
-#pragma unroll
-                for (int k = 0; k < FIT_UNROLL; ++k)
-                    x[k] = *(const int2 *)(lab + (size_t)u[k] * ld + c0);
-#pragma unroll
-                for (int k = 0; k < FIT_UNROLL; ++k) {
-                    cnt0 += x[k].x == own.x;
-                    cnt1 += x[k].y == own.y;
-                }
+        for (int k = 0; k < FIT_ARCS; ++k) {
+            const int32_t ek = min(e + k, a1 - 1);
+            while (ek >= src_end) {  // uniform: advance to the arc's source node
+                ++src;
+                src_end = g.row_ptr[src + 1];
             }
-            for (; e < re; ++e) {
-                const int2 x = *(const int2 *)(lab + (size_t)g.col[e] * ld + c0);
-                cnt0 += x.x == own.x;
-                cnt1 += x.y == own.y;
-            }
-            const int32_t d = re - rs;
-            if (d > 0) {
-                atomicAdd(D + (size_t)own.x * ld + c0, d);
-                if (act1) atomicAdd(D + (size_t)own.y * ld + c0 + 1, d);
+            u[k] = g.col[ek];
+            sv[k] = src;
+        }
+        int2 x[FIT_ARCS], y[FIT_ARCS];
+#pragma unroll
+        for (int k = 0; k < FIT_ARCS; ++k) {
+            x[k] = *(const int2 *)(lc + (size_t)u[k] * ld);
+            y[k] = *(const int2 *)(lc + (size_t)sv[k] * ld);
+        }
+#pragma unroll
+        for (int k = 0; k < FIT_ARCS; ++k) {
+            const bool ok = e + k < a1;
+            cnt0 += ok && x[k].x == y[k].x;
+            cnt1 += ok && x[k].y == y[k].y;
+        }
+    }
+
+    // phase 2: community degree sums and S (telescoping squares)
+    unsigned long long s0 = 0, s1 = 0;
+    if (atomics_phase)
+    for (int32_t vb = v0; vb < v1; vb += FIT_NODES) {
+        int2 own[FIT_NODES];
+        int32_t d[FIT_NODES];
+#pragma unroll
+        for (int k = 0; k < FIT_NODES; ++k) {
+            const int32_t v = min(vb + k, v1 - 1);
+            d[k] = (vb + k < v1) ? g.row_ptr[v + 1] - g.row_ptr[v] : 0;
+            own[k] = *(const int2 *)(lc + (size_t)v * ld);
+        }
+        int o0[FIT_NODES], o1[FIT_NODES];
+#pragma unroll
+        for (int k = 0; k < FIT_NODES; ++k) {
+            o0[k] = o1[k] = 0;
+            if (d[k] > 0) {
+                o0[k] = atomicAdd(D + (size_t)own[k].x * ld + c0, d[k]);
+                if (act1) o1[k] = atomicAdd(D + (size_t)own[k].y * ld + c0 + 1, d[k]);
             }
         }
-        atomicAdd(A + c0, (unsigned long long)cnt0);
-        if (act1) atomicAdd(A + c0 + 1, (unsigned long long)cnt1);
+#pragma unroll
+        for (int k = 0; k < FIT_NODES; ++k) {
+            s0 += sq_step(o0[k], d[k]);
+            s1 += sq_step(o1[k], d[k]);
+        }
     }
+    atomicAdd(A + c0, (unsigned long long)cnt0);
+    if (act1) atomicAdd(A + c0 + 1, (unsigned long long)cnt1);
+    if (atomics_phase) {
+        atomicAdd(S + c0, s0);
+        if (act1) atomicAdd(S + c0 + 1, s1);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Binned community-degree histogram. Atomics on global memory are executed at the memory
+// side on this part whatever the histogram's footprint, at a few times 10^10 per second, so
+// the n x pop scattered additions of the plain histogram dominate the evaluation. Instead:
+//  pass 1 (k_bin): a workgroup takes nb nodes x 16 individuals, counts the (label tile,
+//   individual) bucket of every pair in LDS, scans the counts, and writes the pairs as
+//   packed words (label mod 2^rbits | deg << rbits) grouped by bucket into its own area,
+//   plus the bucket offsets;
+//  pass 2 (k_hist): a workgroup per (tile, individual) gathers that bucket's runs from every
+//   chunk into an LDS histogram of 2^rbits counters and adds sum D_c^2 to S.
+// Every addition happens in LDS; the only global atomic is one per pass-2 workgroup.
+// ---------------------------------------------------------------------------------------
+HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg)
+{
+    HistPlan p;
+    int rb = 0;
+    while ((1 << rb) < n && rb < 14) ++rb;  // tiles of up to 16384 labels (64 KB of LDS)
+    p.rbits = rb;
+    p.tiles = (int32_t)(((int64_t)n + (1 << rb) - 1) >> rb);
+    const int counters = p.tiles * HB_CG;
+    const int budget_words = 16384 - 64;     // 64 KB of LDS: counters, staging, scan partials
+    int nb = (budget_words - counters - 1) / HB_CG;
+    nb = nb / 64 * 64;
+    if (nb > 1024) nb = 1024;
+    p.nb = nb;
+    // the plain histogram's n * pop global atomics are cheap for small problems, where the
+    // two extra launches would cost more than they save
+    p.enabled = nb >= 64 && (int64_t)max_deg < ((int64_t)1 << (32 - rb)) &&
+                (int64_t)n * pop >= ((int64_t)1 << 20);
+    if (!p.enabled) return p;
+    p.nchunks = (n + nb - 1) / nb;
+    p.ngroups = (pop + HB_CG - 1) / HB_CG;
+    p.entries = (size_t)p.ngroups * p.nchunks * (size_t)nb * HB_CG;
+    p.offsets = (size_t)p.ngroups * p.nchunks * (size_t)(counters + 1);
+    return p;
+}
+
+// block-wide exclusive scan of one value per thread (blockDim = 256); returns the prefix
+// and writes the block total to *total
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *wsum, uint32_t *total)
+{
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wv] = x;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+        if (w < wv) base += wsum[w];
+        tot += wsum[w];
+    }
+    *total = tot;
+    return base + x - v;
+}
+
+constexpr int BIN_UNROLL = 4;
+
+__global__ __launch_bounds__(256) void k_bin(DevGraph g, const int32_t *__restrict__ lab,
+                                             int32_t ld, int32_t pop, HistPlan p,
+                                             uint32_t *__restrict__ run,
+                                             uint32_t *__restrict__ off)
+{
+    extern __shared__ uint32_t bl[];
+    const int counters = p.tiles * HB_CG;
+    uint32_t *cnt = bl;                             // [counters + 1]
+    uint32_t *stage = bl + counters + 1;            // [nb * 16]
+    uint32_t *wsum = stage + (size_t)p.nb * HB_CG;  // [4]
+    const int chunk = blockIdx.x, grp = blockIdx.y;
+    const int32_t v0 = chunk * p.nb;
+    const int nv = min(p.nb, g.n - v0);
+    const int cg = min(HB_CG, pop - grp * HB_CG);
+    const int j0 = grp * HB_CG;
+    const uint32_t rmask = (1u << p.rbits) - 1u;
+    for (int i = threadIdx.x; i <= counters; i += blockDim.x) cnt[i] = 0;
+    __syncthreads();
+    // items it = 16 * (v - v0) + jl: a wave reads four 64-byte row segments
+    const int items = nv * HB_CG;
+    for (int base = 0; base < items; base += (int)blockDim.x * BIN_UNROLL) {
+        uint32_t x[BIN_UNROLL];
+        bool ok[BIN_UNROLL];
+#pragma unroll
+        for (int k = 0; k < BIN_UNROLL; ++k) {
+            const int it = base + k * (int)blockDim.x + (int)threadIdx.x;
+            ok[k] = it < items && (it & (HB_CG - 1)) < cg;
+            x[k] = ok[k] ? (uint32_t)lab[(size_t)(v0 + (it >> 4)) * ld + j0 + (it & (HB_CG - 1))] : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < BIN_UNROLL; ++k) {
+            const int it = base + k * (int)blockDim.x + (int)threadIdx.x;
+            if (ok[k]) atomicAdd(&cnt[(x[k] >> p.rbits) * HB_CG + (it & (HB_CG - 1))], 1u);
+        }
+    }
+    __syncthreads();
+    // exclusive scan of the counters: each thread scans a contiguous slice
+    const int per = (counters + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int a = min((int)threadIdx.x * per, counters), b = min(a + per, counters);
+    uint32_t sum = 0;
+    for (int i = a; i < b; ++i) sum += cnt[i];
+    uint32_t total;
+    uint32_t acc = block_exclusive_scan(sum, wsum, &total);
+    __syncthreads();
+    for (int i = a; i < b; ++i) {
+        const uint32_t v = cnt[i];
+        cnt[i] = acc;
+        acc += v;
+    }
+    if (threadIdx.x == 0) cnt[counters] = total;
+    __syncthreads();
+    uint32_t *o = off + ((size_t)chunk * p.ngroups + grp) * (size_t)(counters + 1);
+    for (int i = threadIdx.x; i <= counters; i += blockDim.x) o[i] = cnt[i];
+    __syncthreads();
+    for (int base = 0; base < items; base += (int)blockDim.x * BIN_UNROLL) {
+        uint32_t x[BIN_UNROLL], d[BIN_UNROLL];
+        bool ok[BIN_UNROLL];
+#pragma unroll
+        for (int k = 0; k < BIN_UNROLL; ++k) {
+            const int it = base + k * (int)blockDim.x + (int)threadIdx.x;
+            ok[k] = it < items && (it & (HB_CG - 1)) < cg;
+            const int32_t v = v0 + (ok[k] ? (it >> 4) : 0);
+            x[k] = ok[k] ? (uint32_t)lab[(size_t)v * ld + j0 + (it & (HB_CG - 1))] : 0u;
+            d[k] = (uint32_t)(g.row_ptr[v + 1] - g.row_ptr[v]);
+        }
+#pragma unroll
+        for (int k = 0; k < BIN_UNROLL; ++k) {
+            const int it = base + k * (int)blockDim.x + (int)threadIdx.x;
+            if (ok[k]) {
+                const uint32_t pos = atomicAdd(&cnt[(x[k] >> p.rbits) * HB_CG + (it & (HB_CG - 1))], 1u);
+                stage[pos] = (x[k] & rmask) | (d[k] << p.rbits);
+            }
+        }
+    }
+    __syncthreads();
+    uint32_t *dst = run + ((size_t)grp * p.nchunks + chunk) * ((size_t)p.nb * HB_CG);
+    for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) dst[i] = stage[i];
+}
+
+constexpr int HIST_UNROLL = 8;
+
+__global__ __launch_bounds__(256) void k_hist(HistPlan p, const uint32_t *__restrict__ run,
+                                              const uint32_t *__restrict__ off,
+                                              unsigned long long *__restrict__ S)
+{
+    extern __shared__ uint32_t hist[];  // [2^rbits], the whole 64 KB at most
+    const int t = blockIdx.x, j = blockIdx.y;
+    const int grp = j / HB_CG, jl = j % HB_CG;
+    const int counters = p.tiles * HB_CG;
+    const int bucket = t * HB_CG + jl;
+    const int R = 1 << p.rbits;
+    for (int i = threadIdx.x; i < R; i += blockDim.x) hist[i] = 0;
+    __syncthreads();
+    const size_t span = (size_t)p.nb * HB_CG;
+    // each thread owns chunks w = tid, tid + 256, ...; their runs are read 8 words at a time
+    for (int w = threadIdx.x; w < p.nchunks; w += blockDim.x) {
+        const uint32_t *o = off + ((size_t)w * p.ngroups + grp) * (size_t)(counters + 1) + bucket;
+        const uint32_t e0 = o[0], e1 = o[1];
+        const uint32_t *src = run + ((size_t)grp * p.nchunks + w) * span;
+        for (uint32_t e = e0; e < e1; e += HIST_UNROLL) {
+            uint32_t x[HIST_UNROLL];
+#pragma unroll
+            for (int k = 0; k < HIST_UNROLL; ++k) x[k] = (e + k < e1) ? src[e + k] : 0u;
+#pragma unroll
+            for (int k = 0; k < HIST_UNROLL; ++k)
+                if (e + k < e1) atomicAdd(&hist[x[k] & (uint32_t)(R - 1)], x[k] >> p.rbits);
+        }
+    }
+    __syncthreads();
+    unsigned long long sq = 0;
+    for (int i = threadIdx.x; i < R; i += blockDim.x) {
+        const unsigned long long h = hist[i];
+        sq += h * h;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
+    if (lane_id() == 0 && sq != 0) atomicAdd(S + j, sq);  // one atomic per wave
 }
 
 hipError_t launch_fitness(const DevGraph &g, const int32_t *lab, int32_t ld, int32_t pop,
-                          int32_t *D, unsigned long long *A, hipStream_t s)
+                          const HistPlan &plan, uint32_t *run, uint32_t *off, int32_t *D,
+                          unsigned long long *A, unsigned long long *S, hipStream_t s)
 {
     const int nchunks = (pop + 127) / 128;
-    const int64_t waves = ((int64_t)g.n + FIT_NODES_PER_WAVE - 1) / FIT_NODES_PER_WAVE * nchunks;
+    // nodes per wave: long runs for streaming the CSR, but at least ~16k waves in flight
+    int npw = g.n / 16384;
+    npw = npw < 1 ? 1 : (npw > 64 ? 64 : npw);
+    const int64_t waves = ((int64_t)g.n + npw - 1) / npw * nchunks;
     const unsigned blocks = (unsigned)((waves + 3) / 4);
-    k_fitness<<<blocks, 256, 0, s>>>(g, lab, ld, pop, nchunks, D, A);
-    return hipGetLastError();
-}
-
-// S = sum_c D_c^2 per individual: a coalesced sweep over the node-major histogram that also
-// clears it for the next evaluation.
-constexpr int SWEEP_ROWS_PER_WAVE = 128;
-
-__global__ __launch_bounds__(256) void k_sweep(int32_t n, int32_t ld, int32_t pop,
-                                               int32_t nchunks, int32_t *__restrict__ D,
-                                               unsigned long long *__restrict__ S)
-{
-    const int lane = lane_id();
-    const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
-    const int chunk = wave % nchunks;
-    const int64_t r0 = (int64_t)(wave / nchunks) * SWEEP_ROWS_PER_WAVE;
-    if (r0 >= n) return;
-    const int64_t r1 = min(r0 + SWEEP_ROWS_PER_WAVE, (int64_t)n);
-    const int c0 = chunk * 128 + 2 * lane;
-    if (c0 >= pop) return;
-    unsigned long long s0 = 0, s1 = 0;
-    int64_t r = r0;
-    for (; r + 4 <= r1; r += 4) {
-        int2 x[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) x[k] = *(const int2 *)(D + (size_t)(r + k) * ld + c0);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            s0 += (unsigned long long)((int64_t)x[k].x * x[k].x);
-            s1 += (unsigned long long)((int64_t)x[k].y * x[k].y);
-            *(int2 *)(D + (size_t)(r + k) * ld + c0) = make_int2(0, 0);
-        }
-    }
-    for (; r < r1; ++r) {
-        const int2 x = *(const int2 *)(D + (size_t)r * ld + c0);
-        s0 += (unsigned long long)((int64_t)x.x * x.x);
-        s1 += (unsigned long long)((int64_t)x.y * x.y);
-        *(int2 *)(D + (size_t)r * ld + c0) = make_int2(0, 0);
-    }
-    atomicAdd(S + c0, s0);
-    if (c0 + 1 < pop) atomicAdd(S + c0 + 1, s1);
-}
-
-hipError_t launch_sweep(int32_t n, const int32_t *, int32_t ld, int32_t pop, int32_t *D,
-                        unsigned long long *S, hipStream_t s)
-{
-    const int nchunks = (pop + 127) / 128;
-    const int64_t waves = ((int64_t)n + SWEEP_ROWS_PER_WAVE - 1) / SWEEP_ROWS_PER_WAVE * nchunks;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
-    k_sweep<<<blocks, 256, 0, s>>>(n, ld, pop, nchunks, D, S);
+    k_fitness<<<blocks, 256, 0, s>>>(g, lab, ld, pop, nchunks, npw, D, A, S,
+                                     plan.enabled ? 0 : 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !plan.enabled) return e;
+    const int counters = plan.tiles * HB_CG;
+    const size_t lds1 = sizeof(uint32_t) * ((size_t)counters + 1 + (size_t)plan.nb * HB_CG + 4);
+    k_bin<<<dim3((unsigned)plan.nchunks, (unsigned)plan.ngroups), 256, lds1, s>>>(g, lab, ld, pop,
+                                                                                 plan, run, off);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t lds2 = sizeof(uint32_t) * ((size_t)1 << plan.rbits);
+    k_hist<<<dim3((unsigned)plan.tiles, (unsigned)pop), 256, lds2, s>>>(plan, run, off, S);
     return hipGetLastError();
 }
 
@@ -267,36 +461,57 @@ __device__ __forceinline__ bool dom(long long b1, long long b2, long long a1, lo
     return b1 <= a1 && b2 <= a2 && (b1 < a1 || b2 < a2);
 }
 
+// Sum over a group of T consecutive lanes (T a power of two dividing 64); every lane of the
+// wave must call it.
+__device__ __forceinline__ int group_sum(int v, int T)
+{
+    for (int o = T >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 // On return: sh.rank[i], sh.crowd[i] for i < N and sh.list[q] = index of the point at
-// crowded-comparison position q.
+// crowded-comparison position q. Point i is served by the T threads [i*T, i*T + T) (T a
+// power of two with N*T <= blockDim, at most 64); each O(N) scan is split over the group.
 __device__ void rank_crowd_order(int N, int64_t m2, SelSmem &sh)
 {
-    const int i = threadIdx.x;
+    int T = 1;
+    while (T < 64 && N * T * 2 <= (int)blockDim.x) T <<= 1;
+    const int i = threadIdx.x / T, sub = threadIdx.x % T;
     const bool act = i < N;
+    const bool owner = act && sub == 0;
     const long long a1 = act ? sh.k1[i] : 0, a2 = act ? sh.k2[i] : 0;
 
     // domination counts, then peel fronts (Deb's fast non-dominated sort)
     int cnt = 0;
-    if (act)
-        for (int j = 0; j < N; ++j) cnt += dom(sh.k1[j], sh.k2[j], a1, a2);
+    if (act) {
+#pragma unroll 4
+        for (int j = sub; j < N; j += T) cnt += dom(sh.k1[j], sh.k2[j], a1, a2);
+    }
+    cnt = group_sum(cnt, T);
     int myrank = (act && cnt == 0) ? 1 : 0;
-    if (act) sh.rank[i] = myrank;
+    if (owner) sh.rank[i] = myrank;
     __syncthreads();
     for (int r = 1;; ++r) {
-        if (i == 0) sh.nlist = 0;
+        if (threadIdx.x == 0) sh.nlist = 0;
         __syncthreads();
-        if (act && myrank == r) sh.list[atomicAdd(&sh.nlist, 1)] = i;
+        if (owner && myrank == r) sh.list[atomicAdd(&sh.nlist, 1)] = i;
         __syncthreads();
         const int nf = sh.nlist;
         if (nf == 0) break;
+        int dec = 0;
         if (act && myrank == 0) {
-            for (int a = 0; a < nf; ++a) {
+#pragma unroll 4
+            for (int a = sub; a < nf; a += T) {
                 const int j = sh.list[a];
-                cnt -= dom(sh.k1[j], sh.k2[j], a1, a2);
+                dec += dom(sh.k1[j], sh.k2[j], a1, a2);
             }
+        }
+        dec = group_sum(dec, T);
+        if (act && myrank == 0) {
+            cnt -= dec;
             if (cnt == 0) {
                 myrank = r + 1;
-                sh.rank[i] = myrank;
+                if (owner) sh.rank[i] = myrank;
             }
         }
         __syncthreads();
@@ -304,25 +519,30 @@ __device__ void rank_crowd_order(int N, int64_t m2, SelSmem &sh)
 
     // crowding distance per front
     int off = 0, l = 0;
-    if (act)
-        for (int j = 0; j < N; ++j) {
+    if (act) {
+#pragma unroll 4
+        for (int j = sub; j < N; j += T) {
             const int rj = sh.rank[j];
             off += rj < myrank;
             l += rj == myrank;
         }
+    }
+    off = group_sum(off, T);
+    l = group_sum(l, T);
     const bool interior_front = act && l > 2;
     double cd = 0.0;
     for (int o = 0; o < 2; ++o) {
         const long long mykey = o == 0 ? a1 : a2;
         int pos = 0;
         if (interior_front) {
-            for (int j = 0; j < N; ++j) {
-                if (sh.rank[j] != myrank) continue;
+#pragma unroll 4
+            for (int j = sub; j < N; j += T) {
                 const long long kj = o == 0 ? sh.k1[j] : sh.k2[j];
-                pos += (kj < mykey) || (kj == mykey && j < i);
+                pos += sh.rank[j] == myrank && ((kj < mykey) || (kj == mykey && j < i));
             }
-            sh.sorted[off + pos] = i;
         }
+        pos = group_sum(pos, T);
+        if (interior_front && sub == 0) sh.sorted[off + pos] = i;
         __syncthreads();
         if (interior_front) {
             if (pos == 0 || pos == l - 1) {
@@ -349,19 +569,21 @@ __device__ void rank_crowd_order(int N, int64_t m2, SelSmem &sh)
         __syncthreads();
     }
     if (act && l <= 2) cd = __builtin_inf();
-    if (act) sh.crowd[i] = cd;
+    if (owner) sh.crowd[i] = cd;
     __syncthreads();
 
     // crowded-comparison order
+    int p = 0;
     if (act) {
-        int p = 0;
-        for (int j = 0; j < N; ++j) {
+#pragma unroll 4
+        for (int j = sub; j < N; j += T) {
             const int rj = sh.rank[j];
             const double cj = sh.crowd[j];
             p += (rj < myrank) || (rj == myrank && (cj > cd || (cj == cd && j < i)));
         }
-        sh.list[p] = i;
     }
+    p = group_sum(p, T);
+    if (owner) sh.list[p] = i;
     __syncthreads();
 }
 
@@ -503,25 +725,72 @@ hipError_t launch_final(const GaConst &c, int64_t m2, const DevState &st, hipStr
 // Thread per (node, offspring). Label of member id at node v:
 //   id < pop ? pool_cur[v][id] : q_cur[v][id - pop].
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_crossover(int32_t n, GaConst c, DevState st,
+// Plurality over an ensemble of ES labels; ties drawn uniformly over the tied labels taken
+// in ascending order (eq. arg_max). The draw is made only when there is a tie.
+template <int ES>
+__device__ __forceinline__ int ensemble_plurality(const int (&L)[ES], uint64_t seed, uint32_t v,
+                                                  uint32_t j, uint32_t g)
+{
+    int cnt[ES];
+    int best = 0;
+#pragma unroll
+    for (int k = 0; k < ES; ++k) {
+        int ck = 0;
+#pragma unroll
+        for (int t = 0; t < ES; ++t) ck += L[t] == L[k];
+        cnt[k] = ck;
+        best = max(best, ck);
+    }
+    bool cand[ES];
+    int nt = 0;
+#pragma unroll
+    for (int k = 0; k < ES; ++k) {
+        bool first = true;
+#pragma unroll
+        for (int t = 0; t < k; ++t) first = first && L[t] != L[k];
+        cand[k] = first && cnt[k] == best;
+        nt += cand[k];
+    }
+    if (nt == 1) {
+        int out = L[0];
+#pragma unroll
+        for (int k = ES - 1; k >= 0; --k)
+            if (cand[k]) out = L[k];
+        return out;
+    }
+    const int want = (int)pick(philox(seed, v, j, g, TAG_XOV).a, (uint32_t)nt);
+    int out = L[0];
+#pragma unroll
+    for (int k = 0; k < ES; ++k) {
+        int below = 0;
+#pragma unroll
+        for (int t = 0; t < ES; ++t) below += cand[t] && L[t] < L[k];
+        if (cand[k] && below == want) out = L[k];
+    }
+    return out;
+}
+
+template <int ES>
+__global__ __launch_bounds__(256) void k_crossover(int32_t n, int32_t nblock, GaConst c,
+                                                   DevState st,
                                                    const int32_t *__restrict__ pool_cur,
                                                    const int32_t *__restrict__ q_cur,
                                                    int32_t *__restrict__ pool_new,
                                                    int32_t *__restrict__ C,
                                                    int32_t *__restrict__ q_next, FastDiv divpop)
 {
-    extern __shared__ int xs[];  // [pop] pos_id, [pop] gate, [pop * es] par_id
-    const int pop = c.pop, es = c.es, ld = c.ld;
+    extern __shared__ int xs[];  // [pop] pos_id, [pop] gate, [pop * ES] par_id
+    const int pop = c.pop, ld = c.ld;
     int *s_pos = xs, *s_gate = xs + pop, *s_par = xs + 2 * pop;
     for (int t = threadIdx.x; t < pop; t += blockDim.x) {
         s_pos[t] = st.pos_id[t];
         s_gate[t] = st.gate[t];
     }
-    for (int t = threadIdx.x; t < pop * es; t += blockDim.x) s_par[t] = st.par_id[t];
+    for (int t = threadIdx.x; t < pop * ES; t += blockDim.x) s_par[t] = st.par_id[t];
     __syncthreads();
     const uint32_t g = (uint32_t)*st.gen;
-    const int64_t v0 = (int64_t)blockIdx.x * NODE_BLOCK;
-    const int nv = (int)min((int64_t)NODE_BLOCK, (int64_t)n - v0);
+    const int64_t v0 = (int64_t)blockIdx.x * nblock;
+    const int nv = (int)min((int64_t)nblock, (int64_t)n - v0);
     const uint32_t items = (uint32_t)nv * (uint32_t)pop;
     for (uint32_t f = threadIdx.x; f < items; f += blockDim.x) {
         const uint32_t q = divpop.div(f);
@@ -535,66 +804,48 @@ __global__ __launch_bounds__(256) void k_crossover(int32_t n, GaConst c, DevStat
         const int gk = s_gate[j];
         int out;
         if (gk >= 0) {
-            id = s_par[j * es + gk];
+            id = s_par[j * ES + gk];
             out = id < pop ? prow[id] : qrow[id];
         } else {
-            int L[HPMOCD_MAX_PARENTS_DEV];
+            int L[ES];
 #pragma unroll
-            for (int k = 0; k < HPMOCD_MAX_PARENTS_DEV; ++k) {
-                if (k < es) {
-                    const int pid = s_par[j * es + k];
-                    L[k] = pid < pop ? prow[pid] : qrow[pid];
-                } else {
-                    L[k] = 0;
-                }
+            for (int k = 0; k < ES; ++k) {
+                const int pid = s_par[j * ES + k];
+                L[k] = pid < pop ? prow[pid] : qrow[pid];
             }
-            // plurality over the ensemble; ties drawn uniformly over the tied labels taken in
-            // ascending order (eq. arg_max)
-            int cnt[HPMOCD_MAX_PARENTS_DEV];
-            int best = 0;
-#pragma unroll
-            for (int k = 0; k < HPMOCD_MAX_PARENTS_DEV; ++k) {
-                int ck = 0;
-#pragma unroll
-                for (int t = 0; t < HPMOCD_MAX_PARENTS_DEV; ++t) ck += (t < es) && L[t] == L[k];
-                cnt[k] = (k < es) ? ck : 0;
-                best = max(best, cnt[k]);
-            }
-            bool cand[HPMOCD_MAX_PARENTS_DEV];
-            int nt = 0;
-#pragma unroll
-            for (int k = 0; k < HPMOCD_MAX_PARENTS_DEV; ++k) {
-                bool first = true;
-#pragma unroll
-                for (int t = 0; t < k; ++t) first = first && L[t] != L[k];
-                cand[k] = (k < es) && first && cnt[k] == best;
-                nt += cand[k];
-            }
-            int want = 0;
-            if (nt > 1) want = (int)pick(philox(c.seed, (uint32_t)v, (uint32_t)j, g, TAG_XOV).a,
-                                         (uint32_t)nt);
-            out = 0;
-#pragma unroll
-            for (int k = 0; k < HPMOCD_MAX_PARENTS_DEV; ++k) {
-                int below = 0;
-#pragma unroll
-                for (int t = 0; t < HPMOCD_MAX_PARENTS_DEV; ++t) below += cand[t] && L[t] < L[k];
-                if (cand[k] && below == want) out = L[k];
-            }
+            out = ensemble_plurality<ES>(L, c.seed, (uint32_t)v, (uint32_t)j, g);
         }
         C[row + j] = out;
         q_next[row + j] = out;
     }
 }
 
+// nodes per workgroup in the per-(node, offspring) kernels: 32 for large graphs, fewer so
+// that small graphs still spread over the chip
+static int node_block(int32_t n)
+{
+    int nb = n / 2048;
+    return nb < 1 ? 1 : (nb > 32 ? 32 : nb);
+}
+
 hipError_t launch_crossover(const DevGraph &g, const GaConst &c, const DevState &st,
                             const int32_t *pool_cur, const int32_t *q_cur, int32_t *pool_new,
                             int32_t *C, int32_t *q_next, hipStream_t s)
 {
-    const unsigned blocks = (unsigned)((g.n + NODE_BLOCK - 1) / NODE_BLOCK);
+    const int nb = node_block(g.n);
+    const unsigned blocks = (unsigned)((g.n + nb - 1) / nb);
     const size_t smem = sizeof(int) * (size_t)c.pop * (size_t)(2 + c.es);
-    k_crossover<<<blocks, 256, smem, s>>>(g.n, c, st, pool_cur, q_cur, pool_new, C, q_next,
-                                          FastDiv((uint32_t)c.pop));
+    const FastDiv fd((uint32_t)c.pop);
+#define HPM_XO(ES_)                                                                          \
+    case ES_:                                                                                \
+        k_crossover<ES_><<<blocks, 256, smem, s>>>(g.n, nb, c, st, pool_cur, q_cur, pool_new, \
+                                                   C, q_next, fd);                           \
+        break;
+    switch (c.es) {
+        HPM_XO(1) HPM_XO(2) HPM_XO(3) HPM_XO(4) HPM_XO(5) HPM_XO(6) HPM_XO(7) HPM_XO(8)
+    default: return hipErrorInvalidValue;
+    }
+#undef HPM_XO
     return hipGetLastError();
 }
 
@@ -668,19 +919,26 @@ __device__ __forceinline__ int lane_plurality(const int32_t *__restrict__ C, int
 constexpr int MUT_WAVES = 4;
 constexpr int MUT_LIST_CAP = 1024;  // mutation items one wave can queue (group * pop)
 
-__global__ __launch_bounds__(256) void k_mutate_small(DevGraph g, GaConst c, DevState st,
-                                                      const int32_t *__restrict__ C,
-                                                      int32_t *__restrict__ q_next,
-                                                      FastDiv divpop)
+// Lane class kernel: nodes list[0..count) all have 1 <= deg <= KMAX. A wave takes a group of
+// G consecutive nodes, draws the MUT word of every (node, offspring) pair, queues the pairs
+// that mutate in LDS, then resolves them one per lane. For KMAX == 16 the register array
+// size is picked per batch (4, 8 or 16) from the batch's largest degree.
+template <int KMAX, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_mutate_lanes(DevGraph g, GaConst c, DevState st,
+                                                             const int32_t *__restrict__ list,
+                                                             int32_t count_nodes,
+                                                             const int32_t *__restrict__ C,
+                                                             int32_t *__restrict__ q_next,
+                                                             FastDiv divpop)
 {
-    __shared__ uint2 items[MUT_WAVES][MUT_LIST_CAP];
+    __shared__ uint2 items[WAVES][MUT_LIST_CAP];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const uint32_t gen = (uint32_t)*st.gen;
     const int pop = c.pop, G = c.mut_group;
-    const int ngroups = (g.n_small + G - 1) / G;
-    for (int grp = blockIdx.x * MUT_WAVES + wv; grp < ngroups; grp += gridDim.x * MUT_WAVES) {
+    const int ngroups = (count_nodes + G - 1) / G;
+    for (int grp = blockIdx.x * WAVES + wv; grp < ngroups; grp += gridDim.x * WAVES) {
         const int base = grp * G;
-        const int gn = min(G, g.n_small - base);
+        const int gn = min(G, count_nodes - base);
         const uint32_t total = (uint32_t)gn * (uint32_t)pop;
         int count = 0;
         for (uint32_t f0 = 0; f0 < total; f0 += 64) {
@@ -690,7 +948,7 @@ __global__ __launch_bounds__(256) void k_mutate_small(DevGraph g, GaConst c, Dev
             if (f < total) {
                 const uint32_t gv = divpop.div(f);
                 const uint32_t j = f - gv * (uint32_t)pop;
-                const int32_t node = g.small_nodes[base + (int)gv];
+                const int32_t node = list[base + (int)gv];
                 const u32x4 w = philox(c.seed, (uint32_t)node, j, gen, TAG_MUT);
                 mut = (uint64_t)w.a < c.thr_m;
                 r = w.b;
@@ -705,29 +963,177 @@ __global__ __launch_bounds__(256) void k_mutate_small(DevGraph g, GaConst c, Dev
             const int idx = b + lane;
             const bool has = idx < count;
             const uint2 it = has ? items[wv][idx] : make_uint2(0u, 0u);
-            const int32_t node = g.small_nodes[base + (int)(it.x >> 16)];
+            const int32_t node = list[base + (int)(it.x >> 16)];
             const int j = (int)(it.x & 0xFFFFu);
             const int32_t rs = g.row_ptr[node];
             const int d = has ? g.row_ptr[node + 1] - rs : 0;
-            const int dmax = wave_max(d);
             const int32_t *nbr = g.col + rs;
             int res;
-            if (dmax <= 4)
-                res = lane_plurality<4>(C, c.ld, j, nbr, d, it.y);
-            else if (dmax <= 8)
-                res = lane_plurality<8>(C, c.ld, j, nbr, d, it.y);
-            else if (dmax <= 16)
-                res = lane_plurality<16>(C, c.ld, j, nbr, d, it.y);
-            else
-                res = lane_plurality<32>(C, c.ld, j, nbr, d, it.y);
+            if constexpr (KMAX == 16) {
+                const int dmax = wave_max(d);
+                if (dmax <= 4)
+                    res = lane_plurality<4>(C, c.ld, j, nbr, d, it.y);
+                else if (dmax <= 8)
+                    res = lane_plurality<8>(C, c.ld, j, nbr, d, it.y);
+                else
+                    res = lane_plurality<16>(C, c.ld, j, nbr, d, it.y);
+            } else {
+                res = lane_plurality<KMAX>(C, c.ld, j, nbr, d, it.y);
+            }
             if (has) q_next[(size_t)node * c.ld + j] = res;
         }
         wave_lds_sync();
     }
 }
 
-// Nodes above SMALL_DEG_MAX: one wave per node; each mutating offspring's neighbour labels
-// are sorted in LDS (bitonic), and the plurality is read off the runs.
+// One item per wave: the d <= 64E neighbour labels sit E per lane at positions
+// p = lane + 64k, are sorted across the wave with a bitonic network (partners in other
+// lanes via shuffles, in the same lane via register swaps), and the plurality is read off
+// the runs with ballots.
+template <int E>
+__device__ __forceinline__ void wave_bitonic(int (&a)[E])
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int kk = 2; kk <= 64 * E; kk <<= 1) {
+#pragma unroll
+        for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+            if (jj >= 64) {
+                const int js = jj / 64;
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const int kp = k ^ js;
+                    if (kp > k) {
+                        const bool up = ((64 * k) & kk) == 0;
+                        const int x = a[k], y = a[kp];
+                        a[k] = up ? min(x, y) : max(x, y);
+                        a[kp] = up ? max(x, y) : min(x, y);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < E; ++k) {
+                    const int p = lane + 64 * k;
+                    const int y = __shfl_xor(a[k], jj);
+                    const bool up = (p & kk) == 0;
+                    const bool lower = (lane & jj) == 0;
+                    a[k] = (lower == up) ? min(a[k], y) : max(a[k], y);
+                }
+            }
+        }
+    }
+}
+
+template <int E>
+__device__ __forceinline__ int wave_plurality(const int32_t *__restrict__ C, int ld, int j,
+                                              const int32_t *__restrict__ nbr, int d, uint32_t r)
+{
+    const int lane = lane_id();
+    int a[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int p = lane + 64 * k;
+        a[k] = p < d ? C[(size_t)nbr[p] * ld + j] : INT_MAX;
+    }
+    wave_bitonic<E>(a);
+    uint64_t St[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int p = lane + 64 * k;
+        int prev = __shfl_up(a[k], 1);
+        if (k > 0) {
+            const int wrap = __shfl(a[k - 1], 63);
+            if (lane == 0) prev = wrap;
+        }
+        St[k] = __ballot(p < d && (p == 0 || a[k] != prev));
+    }
+    const uint64_t above = lane == 63 ? 0ull : (~0ull << (lane + 1));
+    int len[E];
+    int mybest = 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int p = lane + 64 * k;
+        int end = d;
+        const uint64_t rest = St[k] & above;
+        if (rest) {
+            end = 64 * k + __builtin_ctzll(rest);
+        } else {
+#pragma unroll
+            for (int k2 = E - 1; k2 > k; --k2)
+                if (St[k2]) end = 64 * k2 + __builtin_ctzll(St[k2]);
+        }
+        end = min(end, d);
+        len[k] = ((St[k] >> lane) & 1ull) ? end - p : 0;
+        mybest = max(mybest, len[k]);
+    }
+    const int best = wave_max(mybest);
+    uint64_t Tm[E];
+    int nt = 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        Tm[k] = __ballot(len[k] == best);
+        nt += __popcll(Tm[k]);
+    }
+    int want = nt > 1 ? (int)pick(r, (uint32_t)nt) : 0;
+    int res = 0;
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int c = __popcll(Tm[k]);
+        if (want >= 0 && want < c) {
+            const bool sel = ((Tm[k] >> lane) & 1ull) && lanes_below(Tm[k]) == want;
+            const int src = __builtin_ctzll(__ballot(sel));
+            res = __shfl(a[k], src);
+        }
+        want -= c;
+    }
+    return res;
+}
+
+// Degree class (64(E/2), 64E]: a wave per node draws the MUT words of all offspring, queues
+// the mutating ones in LDS and resolves them one at a time with the wave sort.
+template <int E>
+__global__ __launch_bounds__(256) void k_mutate_wave(DevGraph g, GaConst c, DevState st,
+                                                     const int32_t *__restrict__ list,
+                                                     int32_t count_nodes,
+                                                     const int32_t *__restrict__ C,
+                                                     int32_t *__restrict__ q_next)
+{
+    __shared__ uint2 items[MUT_WAVES][HPMOCD_MAX_POP_DEV];
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    const uint32_t gen = (uint32_t)*st.gen;
+    const int pop = c.pop, ld = c.ld;
+    for (int t = blockIdx.x * MUT_WAVES + wv; t < count_nodes; t += gridDim.x * MUT_WAVES) {
+        const int32_t node = list[t];
+        const int32_t rs = g.row_ptr[node];
+        const int d = g.row_ptr[node + 1] - rs;
+        const int32_t *nbr = g.col + rs;
+        int count = 0;
+        for (int j0 = 0; j0 < pop; j0 += 64) {
+            const int j = j0 + lane;
+            bool mut = false;
+            uint32_t r = 0;
+            if (j < pop) {
+                const u32x4 w = philox(c.seed, (uint32_t)node, (uint32_t)j, gen, TAG_MUT);
+                mut = (uint64_t)w.a < c.thr_m;
+                r = w.b;
+            }
+            const uint64_t bal = __ballot(mut);
+            if (mut) items[wv][count + lanes_below(bal)] = make_uint2((uint32_t)j, r);
+            count += __popcll(bal);
+        }
+        wave_lds_sync();
+        for (int it = 0; it < count; ++it) {
+            const uint2 item = items[wv][it];
+            const int out = wave_plurality<E>(C, ld, (int)item.x, nbr, d, item.y);
+            if (lane == 0) q_next[(size_t)node * ld + item.x] = out;
+        }
+        wave_lds_sync();
+    }
+}
+
+// Nodes above the wave classes: a workgroup per node; its four waves take the node's
+// mutating offspring in turn, each sorting the neighbour labels in its own LDS buffer
+// (bitonic), then reading the plurality off the runs.
 __device__ __forceinline__ int upper_bound_lds(const int *buf, int lo, int hi, int x)
 {
     while (lo < hi) {
@@ -740,44 +1146,120 @@ __device__ __forceinline__ int upper_bound_lds(const int *buf, int lo, int hi, i
     return lo;
 }
 
-__global__ __launch_bounds__(64) void k_mutate_large(DevGraph g, GaConst c, DevState st,
-                                                     const int32_t *__restrict__ C,
-                                                     int32_t *__restrict__ q_next)
+// plurality of d labels sorted ascending in buf (wave-cooperative)
+__device__ int sorted_plurality(const int *buf, int d, uint32_t r, int *res_slot)
 {
-    __shared__ uint2 items[HPMOCD_MAX_POP_DEV];
-    __shared__ int buf[LARGE_SORT_CAP];
-    __shared__ int result;
-    const int lane = threadIdx.x;
+    const int lane = lane_id();
+    int mybest = 0;
+    for (int i = lane; i < d; i += 64)
+        if (i == 0 || buf[i] != buf[i - 1]) mybest = max(mybest, upper_bound_lds(buf, i, d, buf[i]) - i);
+    const int best = wave_max(mybest);
+    int nt = 0;
+    for (int i0 = 0; i0 < d; i0 += 64) {
+        const int i = i0 + lane;
+        const bool q = i < d && (i == 0 || buf[i] != buf[i - 1]) &&
+                       upper_bound_lds(buf, i, d, buf[i]) - i == best;
+        nt += __popcll(__ballot(q));
+    }
+    int want = nt > 1 ? (int)pick(r, (uint32_t)nt) : 0;
+    for (int i0 = 0; i0 < d; i0 += 64) {
+        const int i = i0 + lane;
+        const bool q = i < d && (i == 0 || buf[i] != buf[i - 1]) &&
+                       upper_bound_lds(buf, i, d, buf[i]) - i == best;
+        const uint64_t bal = __ballot(q);
+        const int cntq = __popcll(bal);
+        if (want < cntq) {
+            if (q && lanes_below(bal) == want) *res_slot = buf[i];
+            break;
+        }
+        want -= cntq;
+    }
+    wave_lds_sync();
+    return *res_slot;
+}
+
+// exact plurality by walking the distinct labels in ascending order (any degree, slow)
+__device__ int scan_plurality(const int32_t *__restrict__ C, int ld, int j,
+                              const int32_t *__restrict__ nbr, int d, uint32_t r)
+{
+    const int lane = lane_id();
+    int best = 0, nt = 0, prev = -1;
+    for (;;) {
+        int mn = INT_MAX;
+        for (int i = lane; i < d; i += 64) {
+            const int x = C[(size_t)nbr[i] * ld + j];
+            if (x > prev) mn = min(mn, x);
+        }
+        mn = wave_min(mn);
+        if (mn == INT_MAX) break;
+        int cn = 0;
+        for (int i = lane; i < d; i += 64) cn += C[(size_t)nbr[i] * ld + j] == mn;
+        cn = wave_sum(cn);
+        if (cn > best) {
+            best = cn;
+            nt = 1;
+        } else if (cn == best) {
+            ++nt;
+        }
+        prev = mn;
+    }
+    const int want = nt > 1 ? (int)pick(r, (uint32_t)nt) : 0;
+    int seen = 0;
+    prev = -1;
+    for (;;) {
+        int mn = INT_MAX;
+        for (int i = lane; i < d; i += 64) {
+            const int x = C[(size_t)nbr[i] * ld + j];
+            if (x > prev) mn = min(mn, x);
+        }
+        mn = wave_min(mn);
+        if (mn == INT_MAX) break;
+        int cn = 0;
+        for (int i = lane; i < d; i += 64) cn += C[(size_t)nbr[i] * ld + j] == mn;
+        cn = wave_sum(cn);
+        if (cn == best) {
+            if (seen == want) return mn;
+            ++seen;
+        }
+        prev = mn;
+    }
+    return prev;  // not reached
+}
+
+__global__ __launch_bounds__(256) void k_mutate_large(DevGraph g, GaConst c, DevState st,
+                                                      const int32_t *__restrict__ C,
+                                                      int32_t *__restrict__ q_next, int pmax)
+{
+    extern __shared__ int lds[];
+    uint2 *items = (uint2 *)lds;                    // [pop]
+    int *res = lds + 2 * HPMOCD_MAX_POP_DEV;        // [MUT_WAVES]
+    int *cnt_sh = res + MUT_WAVES;                  // [1]
+    const int wv = threadIdx.x >> 6, lane = lane_id();
+    int *buf = cnt_sh + 4 + wv * pmax;              // [pmax] per wave
     const uint32_t gen = (uint32_t)*st.gen;
     const int pop = c.pop, ld = c.ld;
     for (int t = blockIdx.x; t < g.n_large; t += gridDim.x) {
         const int32_t node = g.large_nodes[t];
         const int32_t rs = g.row_ptr[node];
         const int d = g.row_ptr[node + 1] - rs;
-        int count = 0;
-        for (int j0 = 0; j0 < pop; j0 += 64) {
-            const int j = j0 + lane;
-            bool mut = false;
-            uint32_t r = 0;
-            if (j < pop) {
-                const u32x4 w = philox(c.seed, (uint32_t)node, (uint32_t)j, gen, TAG_MUT);
-                mut = (uint64_t)w.a < c.thr_m;
-                r = w.b;
-            }
-            const uint64_t bal = __ballot(mut);
-            if (mut) items[count + lanes_below(bal)] = make_uint2((uint32_t)j, r);
-            count += __popcll(bal);
+        const int32_t *nbr = g.col + rs;
+        if (threadIdx.x == 0) *cnt_sh = 0;
+        __syncthreads();
+        for (int j = threadIdx.x; j < pop; j += blockDim.x) {
+            const u32x4 w = philox(c.seed, (uint32_t)node, (uint32_t)j, gen, TAG_MUT);
+            if ((uint64_t)w.a < c.thr_m) items[atomicAdd(cnt_sh, 1)] = make_uint2((uint32_t)j, w.b);
         }
         __syncthreads();
-        for (int it = 0; it < count; ++it) {
+        const int count = *cnt_sh;
+        for (int it = wv; it < count; it += MUT_WAVES) {
             const int j = (int)items[it].x;
             const uint32_t r = items[it].y;
-            if (d <= LARGE_SORT_CAP) {
+            int out;
+            if (d <= pmax) {
                 int P = 64;
                 while (P < d) P <<= 1;
-                for (int i = lane; i < P; i += 64)
-                    buf[i] = i < d ? C[(size_t)g.col[rs + i] * ld + j] : INT_MAX;
-                __syncthreads();
+                for (int i = lane; i < P; i += 64) buf[i] = i < d ? C[(size_t)nbr[i] * ld + j] : INT_MAX;
+                wave_lds_sync();
                 for (int k = 2; k <= P; k <<= 1)
                     for (int jj = k >> 1; jj > 0; jj >>= 1) {
                         for (int i = lane; i < P; i += 64) {
@@ -791,84 +1273,16 @@ __global__ __launch_bounds__(64) void k_mutate_large(DevGraph g, GaConst c, DevS
                                 }
                             }
                         }
-                        __syncthreads();
+                        wave_lds_sync();
                     }
-                int mybest = 0;
-                for (int i = lane; i < d; i += 64)
-                    if (i == 0 || buf[i] != buf[i - 1])
-                        mybest = max(mybest, upper_bound_lds(buf, i, d, buf[i]) - i);
-                const int best = wave_max(mybest);
-                int nt = 0;
-                for (int i0 = 0; i0 < d; i0 += 64) {
-                    const int i = i0 + lane;
-                    const bool q = i < d && (i == 0 || buf[i] != buf[i - 1]) &&
-                                   upper_bound_lds(buf, i, d, buf[i]) - i == best;
-                    nt += __popcll(__ballot(q));
-                }
-                int want = nt > 1 ? (int)pick(r, (uint32_t)nt) : 0;
-                for (int i0 = 0; i0 < d; i0 += 64) {
-                    const int i = i0 + lane;
-                    const bool q = i < d && (i == 0 || buf[i] != buf[i - 1]) &&
-                                   upper_bound_lds(buf, i, d, buf[i]) - i == best;
-                    const uint64_t bal = __ballot(q);
-                    const int cntq = __popcll(bal);
-                    if (want < cntq) {
-                        if (q && lanes_below(bal) == want) result = buf[i];
-                        break;
-                    }
-                    want -= cntq;
-                }
+                out = sorted_plurality(buf, d, r, res + wv);
             } else {
-                // degree above the LDS sort capacity: walk the distinct labels in ascending
-                // order by repeated minimum extraction (slow, exact)
-                int best = 0, nt = 0, prev = -1;
-                for (;;) {
-                    int mn = INT_MAX;
-                    for (int i = lane; i < d; i += 64) {
-                        const int x = C[(size_t)g.col[rs + i] * ld + j];
-                        if (x > prev) mn = min(mn, x);
-                    }
-                    mn = wave_min(mn);
-                    if (mn == INT_MAX) break;
-                    int cn = 0;
-                    for (int i = lane; i < d; i += 64) cn += C[(size_t)g.col[rs + i] * ld + j] == mn;
-                    cn = wave_sum(cn);
-                    if (cn > best) {
-                        best = cn;
-                        nt = 1;
-                    } else if (cn == best) {
-                        ++nt;
-                    }
-                    prev = mn;
-                }
-                const int want = nt > 1 ? (int)pick(r, (uint32_t)nt) : 0;
-                int seen = 0;
-                prev = -1;
-                for (;;) {
-                    int mn = INT_MAX;
-                    for (int i = lane; i < d; i += 64) {
-                        const int x = C[(size_t)g.col[rs + i] * ld + j];
-                        if (x > prev) mn = min(mn, x);
-                    }
-                    mn = wave_min(mn);
-                    if (mn == INT_MAX) break;
-                    int cn = 0;
-                    for (int i = lane; i < d; i += 64) cn += C[(size_t)g.col[rs + i] * ld + j] == mn;
-                    cn = wave_sum(cn);
-                    if (cn == best) {
-                        if (seen == want) {
-                            if (lane == 0) result = mn;
-                            break;
-                        }
-                        ++seen;
-                    }
-                    prev = mn;
-                }
+                out = scan_plurality(C, ld, j, nbr, d, r);
             }
-            __syncthreads();
-            if (lane == 0) q_next[(size_t)node * ld + j] = result;
-            __syncthreads();
+            if (lane == 0) q_next[(size_t)node * ld + j] = out;
+            wave_lds_sync();
         }
+        __syncthreads();
     }
 }
 
@@ -876,18 +1290,43 @@ hipError_t launch_mutation(const DevGraph &g, const GaConst &c, const DevState &
                            const int32_t *C, int32_t *q_next, hipStream_t s)
 {
     if (c.thr_m == 0) return hipSuccess;  // no node can mutate
-    if (g.n_small > 0) {
-        const int ngroups = (g.n_small + c.mut_group - 1) / c.mut_group;
-        int blocks = (ngroups + MUT_WAVES - 1) / MUT_WAVES;
-        if (blocks > 4096) blocks = 4096;
-        k_mutate_small<<<blocks, 64 * MUT_WAVES, 0, s>>>(g, c, st, C, q_next,
-                                                          FastDiv((uint32_t)c.pop));
+    const FastDiv fd((uint32_t)c.pop);
+    int start = 0;
+    for (int k = 0; k < N_DEG_CLASSES; ++k) {
+        const int end = g.class_end[k];
+        const int cnt = end - start;
+        const int32_t *list = g.small_nodes + start;
+        start = end;
+        if (cnt <= 0) continue;
+        const int cls = DEG_CLASS_MAX[k];
+        if (cls <= 32) {
+            const int ngroups = (cnt + c.mut_group - 1) / c.mut_group;
+            int b = (ngroups + MUT_WAVES - 1) / MUT_WAVES;
+            const unsigned blocks = (unsigned)(b > 8192 ? 8192 : b);
+            if (cls == 16)
+                k_mutate_lanes<16, MUT_WAVES><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next, fd);
+            else
+                k_mutate_lanes<32, MUT_WAVES><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next, fd);
+        } else {
+            int b = (cnt + MUT_WAVES - 1) / MUT_WAVES;
+            const unsigned blocks = (unsigned)(b > 16384 ? 16384 : b);
+            switch (cls) {
+            case 64: k_mutate_wave<1><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
+            case 128: k_mutate_wave<2><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
+            case 256: k_mutate_wave<4><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
+            default: k_mutate_wave<8><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
+            }
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     if (g.n_large > 0) {
-        int blocks = g.n_large < 8192 ? g.n_large : 8192;
-        k_mutate_large<<<blocks, 64, 0, s>>>(g, c, st, C, q_next);
+        int pmax = 64;
+        while (pmax < g.large_max_deg && pmax < LARGE_SORT_CAP) pmax <<= 1;
+        const size_t smem = sizeof(int) * (2 * (size_t)HPMOCD_MAX_POP_DEV + MUT_WAVES + 4 +
+                                           (size_t)MUT_WAVES * pmax);
+        const int blocks = g.n_large < 8192 ? g.n_large : 8192;
+        k_mutate_large<<<blocks, 64 * MUT_WAVES, smem, s>>>(g, c, st, C, q_next, pmax);
         return hipGetLastError();
     }
     return hipSuccess;

@@ -63,13 +63,16 @@ def assert_states_equal(gs, os_):
 # ---------------------------------------------------------------------------------------
 # fitness kernel alone
 # ---------------------------------------------------------------------------------------
-@pytest.mark.parametrize("gname", ["fig1", "appendix", "small_1k", "isolated", "star70"])
+@pytest.mark.parametrize("gname", ["fig1", "appendix", "small_1k", "isolated", "star70",
+                                   "mid_40k"])
 @pytest.mark.parametrize("n_ind", [1, 3, 64, 100, 129, 300])
 def test_eval_matches_oracle(hp, stream, gname, n_ind):
+    """Small problems use the plain histogram, |V| = 40,000 with 27 or more individuals the
+    binned one (both for ragged individual counts)."""
     import torch
     g = {"fig1": synth.fig1_graph, "appendix": synth.appendix_graph, "small_1k": synth.small_1k,
          "isolated": lambda: synth.with_isolated(synth.gnp(90, 0.08, 1), 13),
-         "star70": lambda: synth.star(70)}[gname]()
+         "star70": lambda: synth.star(70), "mid_40k": lambda: synth.mid_40k(0.5)}[gname]()
     say(f"eval {gname} n={g.n} n_ind={n_ind}")
     rng = np.random.default_rng(n_ind)
     labs = []
@@ -149,16 +152,24 @@ def test_graph_replay_equals_plain_launches(hp, stream):
 
 
 def test_high_degree_mutation_paths(hp, stream):
-    """Hubs above the per-lane limit (32), and above the LDS sort capacity (4096)."""
+    """Every mutation work class: degrees up to 16 and 32 (one item per lane), 33-64,
+    65-128, 129-256, 257-512 (one item per wave, cross-lane sort), 513-2048 (LDS sort) and
+    above 2048 (exact scan)."""
     rng = np.random.default_rng(0)
-    hub_edges = [(0, i) for i in range(1, 5001)] + [(1, i) for i in range(2, 200)]
-    extra = rng.integers(0, 5001, size=(6000, 2))
-    g = synth.csr_from_edges(5001, np.concatenate([np.array(hub_edges), extra]))
-    say(f"hubs n={g.n} maxdeg={np.diff(g.row_ptr).max()}")
-    got, ref, gs, os_ = traced_pair(hp, stream, g, threads=4, pop_size=20, generations=4,
-                                    mutation_p=0.6, seed=5)
-    assert_states_equal(gs, os_)
-    assert_front_equal(got, ref)
+    n = 5001
+    edges = [(0, i) for i in range(1, 5001)]                      # degree 5000
+    for hub, deg in [(1, 1500), (2, 700), (3, 300), (4, 200), (5, 100), (6, 50), (7, 20)]:
+        nb = rng.choice(np.arange(8, n), size=deg, replace=False)
+        edges += [(hub, int(u)) for u in nb]
+    extra = rng.integers(8, n, size=(6000, 2))
+    g = synth.csr_from_edges(n, np.concatenate([np.array(edges), extra]))
+    deg = np.diff(g.row_ptr)
+    say(f"hubs n={g.n} degrees={sorted(deg)[-8:]}")
+    for mp, seed in [(0.6, 5), (1.0, 6)]:
+        got, ref, gs, os_ = traced_pair(hp, stream, g, threads=4, pop_size=20, generations=3,
+                                        mutation_p=mp, seed=seed)
+        assert_states_equal(gs, os_)
+        assert_front_equal(got, ref)
 
 
 @pytest.mark.parametrize("mu", [0.1, 0.7])
