@@ -103,6 +103,7 @@ typedef struct {
 
 #define HPMOCD_NO_GRAPH 1      /* launch each kernel (no hipGraph replay of the loop) */
 #define HPMOCD_TIME_KERNELS 2  /* record events around every kernel group (implies NO_GRAPH) */
+#define HPMOCD_TRACE_NO_LABELS 4 /* trace callback gets labels = NULL (objectives only) */
 
 /* Builds the device graph from a symmetric CSR (row_ptr[n+1], col[row_ptr[n]]).
  * Validates it (codes above; section 2.1 requires a simple undirected graph), sorts every

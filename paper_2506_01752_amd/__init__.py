@@ -26,6 +26,7 @@ MAX_POP = 512
 MAX_PARENTS = 8
 NO_GRAPH = 1
 TIME_KERNELS = 2
+TRACE_NO_LABELS = 4
 
 # every entry point that include/hpmocd.h declares
 EXPORTS = [
@@ -239,7 +240,8 @@ def run(graph: Graph, params: Params | None = None, *, stream=None, workspace=No
             v = vp.contents
             np_, nn = v.pop_size, v.n_nodes
             on_generation(State(
-                v.g, np.ctypeslib.as_array(v.labels, shape=(np_, nn)).copy(),
+                v.g,
+                np.ctypeslib.as_array(v.labels, shape=(np_, nn)).copy() if v.labels else None,
                 np.ctypeslib.as_array(v.A, shape=(np_,)).copy(),
                 np.ctypeslib.as_array(v.S, shape=(np_,)).copy(),
                 np.ctypeslib.as_array(v.f1, shape=(np_,)).copy(),

@@ -22,7 +22,7 @@ struct hpmocd_graph {
     int device = 0;
     int32_t *d_rp = nullptr, *d_col = nullptr, *d_small = nullptr, *d_large = nullptr;
     int32_t n_small = 0, n_large = 0;
-    int32_t class_end[N_DEG_CLASSES] = {0, 0, 0, 0, 0, 0};
+    int32_t class_end[N_DEG_CLASSES] = {};
     int32_t large_max_deg = 0;
 };
 
@@ -203,15 +203,17 @@ hipError_t generation(const DevGraph &g, const GaConst &c, const RunLayout &L, i
 
 // Host copy of P (selection order) as rows, for the trace callback.
 int emit_state(const hpmocd_graph *G, const GaConst &c, const RunLayout &L, int cur, int32_t gen,
-               hipStream_t s, hpmocd_trace_fn fn, void *user)
+               hipStream_t s, hpmocd_trace_fn fn, void *user, bool with_labels)
 {
     const int32_t n = G->n, pop = c.pop, ld = c.ld;
-    std::vector<int32_t> pool((size_t)n * ld), q((size_t)n * ld), ids(pop), rank(pop);
+    const size_t plane_cells = with_labels ? (size_t)n * ld : 0;
+    std::vector<int32_t> pool(plane_cells), q(plane_cells), ids(pop), rank(pop);
     std::vector<int64_t> A(pop), S(pop);
     std::vector<double> f1(pop), f2(pop), crowd(pop);
     HIP_TRY(hipStreamSynchronize(s));
-    if (gen > 0) HIP_TRY(hipMemcpy(pool.data(), L.pool[cur], L.plane, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(q.data(), L.q[cur], L.plane, hipMemcpyDeviceToHost));
+    if (with_labels && gen > 0)
+        HIP_TRY(hipMemcpy(pool.data(), L.pool[cur], L.plane, hipMemcpyDeviceToHost));
+    if (with_labels) HIP_TRY(hipMemcpy(q.data(), L.q[cur], L.plane, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(ids.data(), L.st.ps_id, sizeof(int32_t) * pop, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(A.data(), L.st.ps_A, sizeof(int64_t) * pop, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(S.data(), L.st.ps_S, sizeof(int64_t) * pop, hipMemcpyDeviceToHost));
@@ -221,8 +223,8 @@ int emit_state(const hpmocd_graph *G, const GaConst &c, const RunLayout &L, int 
         HIP_TRY(hipMemcpy(rank.data(), L.st.tr_rank, sizeof(int32_t) * pop, hipMemcpyDeviceToHost));
         HIP_TRY(hipMemcpy(crowd.data(), L.st.tr_crowd, sizeof(double) * pop, hipMemcpyDeviceToHost));
     }
-    std::vector<int32_t> rows((size_t)pop * n);
-    for (int32_t i = 0; i < pop; ++i) {
+    std::vector<int32_t> rows(with_labels ? (size_t)pop * n : 0);
+    for (int32_t i = 0; with_labels && i < pop; ++i) {
         const int32_t id = ids[i];
         const int32_t *src = id < pop ? pool.data() + id : q.data() + (id - pop);
         int32_t *dst = rows.data() + (size_t)i * n;
@@ -232,7 +234,7 @@ int emit_state(const hpmocd_graph *G, const GaConst &c, const RunLayout &L, int 
     view.g = gen;
     view.pop_size = pop;
     view.n_nodes = n;
-    view.labels = rows.data();
+    view.labels = with_labels ? rows.data() : nullptr;
     view.A = A.data();
     view.S = S.data();
     view.f1 = f1.data();
@@ -461,6 +463,7 @@ int hpmocd_run_ex(const hpmocd_graph *G, const hpmocd_params *p, void *ws, size_
     const DevGraph dg = dev_graph(G);
     const GaConst c = ga_const(p, L.ld);
     const bool time_kernels = (flags & HPMOCD_TIME_KERNELS) != 0 && prof;
+    const bool trace_labels = (flags & HPMOCD_TRACE_NO_LABELS) == 0;
     const bool use_graph = !(flags & (HPMOCD_NO_GRAPH | HPMOCD_TIME_KERNELS)) && !trace &&
                            s != nullptr && T >= 2;
 
@@ -504,7 +507,7 @@ int hpmocd_run_ex(const hpmocd_graph *G, const hpmocd_params *p, void *ws, size_
     if (prof) HIP_TRY(hipEventRecord(e_sw1, s));
     HIP_TRY(launch_init_state(c, G->m2, L.st, s));
     int cur = 0;
-    if (trace && (rc = emit_state(G, c, L, cur, 0, s, trace, user))) return rc;
+    if (trace && (rc = emit_state(G, c, L, cur, 0, s, trace, user, trace_labels))) return rc;
 
     double fit_ms = 0, sweep_ms = 0, var_ms = 0, sel_ms = 0;
     if (prof) HIP_TRY(hipEventRecord(e_loop0, s));
@@ -534,7 +537,7 @@ int hpmocd_run_ex(const hpmocd_graph *G, const hpmocd_params *p, void *ws, size_
         std::vector<EventPair> *ev = time_kernels ? &gen_events[(size_t)(gen - 1)] : nullptr;
         HIP_TRY(generation(dg, c, L, cur, s, ev));
         cur = 1 - cur;
-        if (trace && (rc = emit_state(G, c, L, cur, gen, s, trace, user))) return rc;
+        if (trace && (rc = emit_state(G, c, L, cur, gen, s, trace, user, trace_labels))) return rc;
     }
     if (prof) HIP_TRY(hipEventRecord(e_loop1, s));
 

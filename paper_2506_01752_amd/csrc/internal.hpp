@@ -24,10 +24,10 @@ constexpr int HPMOCD_MAX_POP_DEV = HPMOCD_MAX_POP;
 // per lane, neighbour labels sorted in registers. Degrees 33..512: one item per wave, the
 // labels spread 1, 2, 4 or 8 per lane and sorted across the wave. Higher degrees: one item
 // per wave with an LDS sort (up to LARGE_SORT_CAP neighbours) or, above that, an exact scan.
-constexpr int N_DEG_CLASSES = 6;
-constexpr int DEG_CLASS_MAX[N_DEG_CLASSES] = {16, 32, 64, 128, 256, 512};
-constexpr int SMALL_DEG_MAX = 512;
-constexpr int LARGE_SORT_CAP = 2048;
+constexpr int N_DEG_CLASSES = 8;
+constexpr int DEG_CLASS_MAX[N_DEG_CLASSES] = {16, 32, 64, 128, 256, 512, 1024, 2048};
+constexpr int SMALL_DEG_MAX = 2048;
+constexpr int LARGE_SORT_CAP = 4096;
 constexpr int SEL_THREADS = 1024;   // selection kernels: one workgroup, one thread per point
 
 struct DevGraph {

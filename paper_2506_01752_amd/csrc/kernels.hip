@@ -295,7 +295,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *w
     return base + x - v;
 }
 
-constexpr int BIN_UNROLL = 4;
+constexpr int BIN_UNROLL = 16;
 
 __global__ __launch_bounds__(256) void k_bin(DevGraph g, const int32_t *__restrict__ lab,
                                              int32_t ld, int32_t pop, HistPlan p,
@@ -391,18 +391,33 @@ __global__ __launch_bounds__(256) void k_hist(HistPlan p, const uint32_t *__rest
     for (int i = threadIdx.x; i < R; i += blockDim.x) hist[i] = 0;
     __syncthreads();
     const size_t span = (size_t)p.nb * HB_CG;
-    // each thread owns chunks w = tid, tid + 256, ...; their runs are read 8 words at a time
-    for (int w = threadIdx.x; w < p.nchunks; w += blockDim.x) {
-        const uint32_t *o = off + ((size_t)w * p.ngroups + grp) * (size_t)(counters + 1) + bucket;
-        const uint32_t e0 = o[0], e1 = o[1];
-        const uint32_t *src = run + ((size_t)grp * p.nchunks + w) * span;
-        for (uint32_t e = e0; e < e1; e += HIST_UNROLL) {
-            uint32_t x[HIST_UNROLL];
+    // each thread owns chunks w = tid + 256 k; the run bounds of up to 8 of them are loaded
+    // together, then the runs are read 8 words at a time
+    constexpr int WPT = 8;
+    for (int w0 = 0; w0 < p.nchunks; w0 += (int)blockDim.x * WPT) {
+        uint32_t b0[WPT], b1[WPT];
 #pragma unroll
-            for (int k = 0; k < HIST_UNROLL; ++k) x[k] = (e + k < e1) ? src[e + k] : 0u;
+        for (int k = 0; k < WPT; ++k) {
+            const int w = w0 + k * (int)blockDim.x + (int)threadIdx.x;
+            b0[k] = b1[k] = 0;
+            if (w < p.nchunks) {
+                const uint32_t *o = off + ((size_t)w * p.ngroups + grp) * (size_t)(counters + 1) + bucket;
+                b0[k] = o[0];
+                b1[k] = o[1];
+            }
+        }
 #pragma unroll
-            for (int k = 0; k < HIST_UNROLL; ++k)
-                if (e + k < e1) atomicAdd(&hist[x[k] & (uint32_t)(R - 1)], x[k] >> p.rbits);
+        for (int k = 0; k < WPT; ++k) {
+            const int w = w0 + k * (int)blockDim.x + (int)threadIdx.x;
+            const uint32_t *src = run + ((size_t)grp * p.nchunks + (size_t)(w < p.nchunks ? w : 0)) * span;
+            for (uint32_t e = b0[k]; e < b1[k]; e += HIST_UNROLL) {
+                uint32_t x[HIST_UNROLL];
+#pragma unroll
+                for (int q = 0; q < HIST_UNROLL; ++q) x[q] = (e + q < b1[k]) ? src[e + q] : 0u;
+#pragma unroll
+                for (int q = 0; q < HIST_UNROLL; ++q)
+                    if (e + q < b1[k]) atomicAdd(&hist[x[q] & (uint32_t)(R - 1)], x[q] >> p.rbits);
+            }
         }
     }
     __syncthreads();
@@ -792,31 +807,44 @@ __global__ __launch_bounds__(256) void k_crossover(int32_t n, int32_t nblock, Ga
     const int64_t v0 = (int64_t)blockIdx.x * nblock;
     const int nv = (int)min((int64_t)nblock, (int64_t)n - v0);
     const uint32_t items = (uint32_t)nv * (uint32_t)pop;
-    for (uint32_t f = threadIdx.x; f < items; f += blockDim.x) {
-        const uint32_t q = divpop.div(f);
-        const int j = (int)(f - q * (uint32_t)pop);
-        const int64_t v = v0 + q;
-        const size_t row = (size_t)v * ld;
-        const int32_t *prow = pool_cur + row;
-        const int32_t *qrow = q_cur + row - pop;  // indexed by id >= pop
-        int id = s_pos[j];
-        pool_new[row + j] = id < pop ? prow[id] : qrow[id];
-        const int gk = s_gate[j];
-        int out;
-        if (gk >= 0) {
-            id = s_par[j * ES + gk];
-            out = id < pop ? prow[id] : qrow[id];
-        } else {
-            int L[ES];
+    // XO_ITEMS (node, offspring) items per thread at once: all their loads are issued
+    // before any plurality is resolved
+    constexpr int XO_ITEMS = 4;
+    for (uint32_t base = 0; base < items; base += blockDim.x * XO_ITEMS) {
+        int commit[XO_ITEMS], L[XO_ITEMS][ES];
+        bool has[XO_ITEMS];
+        size_t row[XO_ITEMS];
+        int jj[XO_ITEMS], gk[XO_ITEMS];
+        uint32_t vv[XO_ITEMS];
+#pragma unroll
+        for (int t = 0; t < XO_ITEMS; ++t) {
+            const uint32_t f = base + t * blockDim.x + threadIdx.x;
+            has[t] = f < items;
+            const uint32_t fq = has[t] ? f : 0u;
+            const uint32_t q = divpop.div(fq);
+            jj[t] = (int)(fq - q * (uint32_t)pop);
+            vv[t] = (uint32_t)(v0 + q);
+            row[t] = (size_t)vv[t] * ld;
+            const int32_t *prow = pool_cur + row[t];
+            const int32_t *qrow = q_cur + row[t] - pop;  // indexed by id >= pop
+            const int id = s_pos[jj[t]];
+            commit[t] = id < pop ? prow[id] : qrow[id];
+            gk[t] = s_gate[jj[t]];
 #pragma unroll
             for (int k = 0; k < ES; ++k) {
-                const int pid = s_par[j * ES + k];
-                L[k] = pid < pop ? prow[pid] : qrow[pid];
+                const int pid = s_par[jj[t] * ES + (gk[t] >= 0 ? gk[t] : k)];
+                L[t][k] = pid < pop ? prow[pid] : qrow[pid];
             }
-            out = ensemble_plurality<ES>(L, c.seed, (uint32_t)v, (uint32_t)j, g);
         }
-        C[row + j] = out;
-        q_next[row + j] = out;
+#pragma unroll
+        for (int t = 0; t < XO_ITEMS; ++t) {
+            if (!has[t]) continue;
+            const int out = gk[t] >= 0 ? L[t][0]
+                                       : ensemble_plurality<ES>(L[t], c.seed, vv[t], (uint32_t)jj[t], g);
+            pool_new[row[t] + jj[t]] = commit[t];
+            C[row[t] + jj[t]] = out;
+            q_next[row[t] + jj[t]] = out;
+        }
     }
 }
 
@@ -1226,7 +1254,7 @@ __device__ int scan_plurality(const int32_t *__restrict__ C, int ld, int j,
     return prev;  // not reached
 }
 
-__global__ __launch_bounds__(256) void k_mutate_large(DevGraph g, GaConst c, DevState st,
+__global__ __launch_bounds__(128) void k_mutate_large(DevGraph g, GaConst c, DevState st,
                                                       const int32_t *__restrict__ C,
                                                       int32_t *__restrict__ q_next, int pmax)
 {
@@ -1235,6 +1263,7 @@ __global__ __launch_bounds__(256) void k_mutate_large(DevGraph g, GaConst c, Dev
     int *res = lds + 2 * HPMOCD_MAX_POP_DEV;        // [MUT_WAVES]
     int *cnt_sh = res + MUT_WAVES;                  // [1]
     const int wv = threadIdx.x >> 6, lane = lane_id();
+    const int nwaves = (int)(blockDim.x >> 6);
     int *buf = cnt_sh + 4 + wv * pmax;              // [pmax] per wave
     const uint32_t gen = (uint32_t)*st.gen;
     const int pop = c.pop, ld = c.ld;
@@ -1251,7 +1280,7 @@ __global__ __launch_bounds__(256) void k_mutate_large(DevGraph g, GaConst c, Dev
         }
         __syncthreads();
         const int count = *cnt_sh;
-        for (int it = wv; it < count; it += MUT_WAVES) {
+        for (int it = wv; it < count; it += nwaves) {
             const int j = (int)items[it].x;
             const uint32_t r = items[it].y;
             int out;
@@ -1314,7 +1343,9 @@ hipError_t launch_mutation(const DevGraph &g, const GaConst &c, const DevState &
             case 64: k_mutate_wave<1><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
             case 128: k_mutate_wave<2><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
             case 256: k_mutate_wave<4><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
-            default: k_mutate_wave<8><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
+            case 512: k_mutate_wave<8><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
+            case 1024: k_mutate_wave<16><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
+            default: k_mutate_wave<32><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
             }
         }
         hipError_t e = hipGetLastError();
@@ -1323,10 +1354,11 @@ hipError_t launch_mutation(const DevGraph &g, const GaConst &c, const DevState &
     if (g.n_large > 0) {
         int pmax = 64;
         while (pmax < g.large_max_deg && pmax < LARGE_SORT_CAP) pmax <<= 1;
+        const int waves = 2;
         const size_t smem = sizeof(int) * (2 * (size_t)HPMOCD_MAX_POP_DEV + MUT_WAVES + 4 +
-                                           (size_t)MUT_WAVES * pmax);
+                                           (size_t)waves * pmax);
         const int blocks = g.n_large < 8192 ? g.n_large : 8192;
-        k_mutate_large<<<blocks, 64 * MUT_WAVES, smem, s>>>(g, c, st, C, q_next, pmax);
+        k_mutate_large<<<blocks, 64 * waves, smem, s>>>(g, c, st, C, q_next, pmax);
         return hipGetLastError();
     }
     return hipSuccess;
