@@ -43,6 +43,25 @@ def population_floor_bytes(n: int, m2: int, pop: int) -> int:
     return 4 * (n + 1) + 4 * m2 + 4 * n * pop
 
 
+def measured_traffic(workload: str, pop: int):
+    """HBM bytes of one fitness step from the committed rocprofv3 counter summary, or None
+    when there is none for this workload or the kernels changed since it was taken."""
+    import hashlib
+    import re
+    if workload != "planted_partition_1M" or pop != 100:
+        return None
+    path = os.path.join(ROOT, "profiles", "traffic_fitness_planted_1M_pop100.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"kernels.hip sha256 prefix when measured: ([0-9a-f]+)", text)
+    m_val = re.search(r"fitness_step_traffic_bytes: (\d+)", text)
+    src = open(os.path.join(ROOT, "paper_2506_01752_amd", "csrc", "kernels.hip"), "rb").read()
+    if not m_sha or not m_val or hashlib.sha256(src).hexdigest()[:16] != m_sha.group(1):
+        return None
+    return int(m_val.group(1))
+
+
 def cpu_baseline(g, seed: int, target_s: float = 15.0):
     """The oracle's evaluation, single-threaded, on a bounded sample of individuals of the
     same workload (the initial population's first rows)."""
@@ -77,7 +96,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph-mode", action="store_true",
                     help="also time runs whose generation loop is replayed from a hipGraph")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (calibrates "
+                         "the memory-traffic counters) and exit")
     args = ap.parse_args()
+    if args.copy_probe_mib:
+        import torch
+        a = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel()}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -150,7 +182,8 @@ def main():
         "population_floor_GBps": population_floor_bytes(g.n, 2 * g.m, pop) / (eval_ms / 1e3) / 1e9,
         "roofline": {"bound": "hbm", "kernel": "fitness (k_fitness + k_bin + k_hist)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic(args.workload, pop),
                      "bytes_per_launch": bytes_launch, "ms_per_launch": eval_ms},
     }
     if args.graph_mode and T >= 2:
