@@ -98,12 +98,18 @@ typedef struct {
     double variation_ms;       /* crossover + mutation kernels */
     double select_ms;          /* ranking / crowding / selection kernels */
     int64_t fitness_launches;  /* number of edge-scan launches */
-    int64_t individual_evals;  /* N_p (T + 1) */
+    int64_t individual_evals;  /* N_p (T + 1), summed over a batch */
+    int32_t tune_fit_target_waves;  /* launch shapes used (autotuned with HPMOCD_AUTOTUNE) */
+    int32_t tune_xo_target_blocks;
+    int32_t tune_mut_target_items;
+    int32_t tune_hist_min_log2;
+    double tune_probe_ms;      /* device time spent probing shapes (0 without autotuning) */
 } hpmocd_profile;
 
 #define HPMOCD_NO_GRAPH 1      /* launch each kernel (no hipGraph replay of the loop) */
 #define HPMOCD_TIME_KERNELS 2  /* record events around every kernel group (implies NO_GRAPH) */
 #define HPMOCD_TRACE_NO_LABELS 4 /* trace callback gets labels = NULL (objectives only) */
+#define HPMOCD_AUTOTUNE 8      /* batches: time candidate launch shapes on the batch first */
 
 /* Builds the device graph from a symmetric CSR (row_ptr[n+1], col[row_ptr[n]]).
  * Validates it (codes above; section 2.1 requires a simple undirected graph), sorts every
@@ -134,6 +140,21 @@ int hpmocd_run_ex(const hpmocd_graph *g, const hpmocd_params *p, void *d_workspa
                   hpmocd_trace_fn trace, void *user, hpmocd_front **out);
 
 void hpmocd_front_free(hpmocd_front *f);
+
+/* Batched form: `count` independent runs of Alg. 1, each on its own graph with its own
+ * population and parameters (params[i]; all with the same generations and
+ * parents_per_child), advanced together: every kernel launch covers all of the batch's
+ * populations, and the generation loop is replayed from one hipGraph. With HPMOCD_AUTOTUNE
+ * the launch shapes (arc-scan waves, crossover workgroups, mutation queue length, histogram
+ * choice) are first timed on two generations of this batch and the fastest kept; results do
+ * not depend on the shapes. Each run's front equals its hpmocd_run front bit for bit.
+ * outs[count] receives one front per run (free each with hpmocd_front_free). The workspace
+ * size depends on the flags (autotuning needs room for both histogram variants). */
+int hpmocd_batch_workspace_size(const hpmocd_graph *const *graphs, int32_t count,
+                                const hpmocd_params *params, int flags, size_t *bytes);
+int hpmocd_run_batch(const hpmocd_graph *const *graphs, int32_t count,
+                     const hpmocd_params *params, void *d_workspace, size_t ws_bytes,
+                     void *stream, int flags, hpmocd_profile *profile, hpmocd_front **outs);
 
 /* Fitness alone (eq. objectives) for n_ind partitions given as device memory, row-major
  * n_ind x n int32 labels in [0, n) (values outside are an error the kernel cannot report:

@@ -27,12 +27,14 @@ MAX_PARENTS = 8
 NO_GRAPH = 1
 TIME_KERNELS = 2
 TRACE_NO_LABELS = 4
+AUTOTUNE = 8
 
 # every entry point that include/hpmocd.h declares
 EXPORTS = [
     "hpmocd_graph_create", "hpmocd_graph_destroy", "hpmocd_graph_info",
     "hpmocd_workspace_size", "hpmocd_run", "hpmocd_run_ex", "hpmocd_front_free",
     "hpmocd_eval_workspace_size", "hpmocd_eval", "hpmocd_strerror",
+    "hpmocd_batch_workspace_size", "hpmocd_run_batch",
 ]
 
 
@@ -67,7 +69,10 @@ class Profile(C.Structure):
     _fields_ = [("total_ms", C.c_double), ("loop_ms", C.c_double),
                 ("fitness_ms", C.c_double), ("sweep_ms", C.c_double),
                 ("variation_ms", C.c_double), ("select_ms", C.c_double),
-                ("fitness_launches", C.c_int64), ("individual_evals", C.c_int64)]
+                ("fitness_launches", C.c_int64), ("individual_evals", C.c_int64),
+                ("tune_fit_target_waves", C.c_int32), ("tune_xo_target_blocks", C.c_int32),
+                ("tune_mut_target_items", C.c_int32), ("tune_hist_min_log2", C.c_int32),
+                ("tune_probe_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -101,6 +106,11 @@ def lib():
         L.hpmocd_eval_workspace_size.argtypes = [vp, C.c_int32, C.POINTER(C.c_size_t)]
         L.hpmocd_eval.argtypes = [vp, vp, C.c_int32, vp, C.c_size_t, vp, i64p, i64p, f64p, f64p,
                                   f64p]
+        L.hpmocd_batch_workspace_size.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(Params),
+                                                  C.c_int, C.POINTER(C.c_size_t)]
+        L.hpmocd_run_batch.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(Params), vp,
+                                       C.c_size_t, vp, C.c_int, C.POINTER(Profile),
+                                       C.POINTER(C.POINTER(_Front))]
         L.hpmocd_strerror.argtypes = [C.c_int]
         L.hpmocd_strerror.restype = C.c_char_p
         for name in EXPORTS:
@@ -255,6 +265,44 @@ def run(graph: Graph, params: Params | None = None, *, stream=None, workspace=No
     _check(st, "hpmocd_run_ex")
     front = _front_from(out)
     return (front, prof.as_dict()) if profile else front
+
+
+def run_batch(graphs, params, *, stream=None, workspace=None, flags=0, profile=False):
+    """hpmocd_run_batch: one run per graph (params: one Params, or one per graph), all
+    advanced together. Returns the list of fronts, or (fronts, profile dict)."""
+    import torch
+    count = len(graphs)
+    if isinstance(params, Params):
+        params = [params] * count
+    assert len(params) == count
+    handles = (C.c_void_p * count)(*[g.handle.value for g in graphs])
+    parr = (Params * count)(*params)
+    b = C.c_size_t()
+    _check(lib().hpmocd_batch_workspace_size(handles, count, parr, flags, C.byref(b)),
+           "hpmocd_batch_workspace_size")
+    ws = workspace if workspace is not None else torch.empty(b.value, dtype=torch.uint8,
+                                                             device="cuda")
+    assert ws.numel() >= b.value and ws.is_cuda
+    prof = Profile()
+    outs = (C.POINTER(_Front) * count)()
+    _check(lib().hpmocd_run_batch(handles, count, parr, C.c_void_p(ws.data_ptr()), b.value,
+                                  _stream_handle(stream), flags,
+                                  C.byref(prof) if profile else None, outs),
+           "hpmocd_run_batch")
+    fronts = [_front_from(outs[i]) for i in range(count)]
+    return (fronts, prof.as_dict()) if profile else fronts
+
+
+def batch_workspace_size(graphs, params, flags=0) -> int:
+    count = len(graphs)
+    if isinstance(params, Params):
+        params = [params] * count
+    handles = (C.c_void_p * count)(*[g.handle.value for g in graphs])
+    parr = (Params * count)(*params)
+    b = C.c_size_t()
+    _check(lib().hpmocd_batch_workspace_size(handles, count, parr, flags, C.byref(b)),
+           "hpmocd_batch_workspace_size")
+    return b.value
 
 
 def evaluate(graph: Graph, labels, *, stream=None, timing=False):

@@ -74,13 +74,11 @@ struct GaConst {
     int32_t mut_group;  // nodes per wave group in the small-degree mutation kernel
 };
 
-// ---- launchers (kernels.hip) -----------------------------------------------------------
-hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
-hipError_t launch_init(const DevGraph &g, const GaConst &c, int32_t *Q, hipStream_t s);
 // Plan of the binned community-degree histogram (see kernels.hip): labels are split into
 // tiles of 2^rbits values; pass 1 bins every (label, degree) pair of a chunk of nb nodes and
 // a group of 16 individuals into runs per (tile, individual); pass 2 builds each tile's
-// histogram in LDS. Used when every degree fits the entry's 32 - rbits bits and nb >= 64.
+// histogram in LDS. Used when every degree fits the entry's 32 - rbits bits, nb >= 64 and the
+// problem has at least 2^min_log2 (node, individual) pairs.
 constexpr int HB_CG = 16;  // individuals per bin group
 struct HistPlan {
     int32_t rbits = 0;     // tile = 2^rbits label values
@@ -91,25 +89,56 @@ struct HistPlan {
     size_t entries = 0;    // uint32 entries of the run area
     size_t offsets = 0;    // uint32 offsets (per chunk and group: tiles * 16 + 1)
 };
-HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg);
+HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2);
 
-// A and S of every individual of a node-major population.
-//  binned (plan.enabled): run/off are work areas of plan.entries / plan.offsets words;
-//  otherwise: D must be all zero on entry and is left holding the community degree sums
-//  (clear it before the next call).
-hipError_t launch_fitness(const DevGraph &g, const int32_t *lab, int32_t ld, int32_t pop,
-                          const HistPlan &plan, uint32_t *run, uint32_t *off, int32_t *D,
-                          unsigned long long *A, unsigned long long *S, hipStream_t s);
-hipError_t launch_init_state(const GaConst &c, int64_t m2, const DevState &st, hipStream_t s);
-hipError_t launch_rank_parents(const GaConst &c, int64_t m2, const DevState &st,
-                               hipStream_t s);
-hipError_t launch_crossover(const DevGraph &g, const GaConst &c, const DevState &st,
-                            const int32_t *pool_cur, const int32_t *q_cur, int32_t *pool_new,
-                            int32_t *C, int32_t *q_next, hipStream_t s);
-hipError_t launch_mutation(const DevGraph &g, const GaConst &c, const DevState &st,
-                           const int32_t *C, int32_t *q_next, hipStream_t s);
-hipError_t launch_select(const GaConst &c, int64_t m2, const DevState &st, hipStream_t s);
-hipError_t launch_final(const GaConst &c, int64_t m2, const DevState &st, hipStream_t s);
+// One population on one graph, as the kernels see it (lives in device memory). A run is a
+// batch of one item; the batched form puts many graphs, each with its own population, into
+// the same launches.
+struct Item {
+    DevGraph g;
+    GaConst c;
+    DevState st;
+    HistPlan hp;
+    const int32_t *pool_cur, *q_cur;     // parent planes of a generation (q_cur: init target)
+    int32_t *pool_new, *C, *q_next;      // crossover / mutation outputs
+    const int32_t *lab;                  // plane the fitness kernels evaluate
+    int32_t fit_pop, fit_ld;             // individuals evaluated and their row stride
+    unsigned long long *fit_A, *fit_S;   // accumulators the fitness kernels add into
+    int32_t *D;                          // plain histogram plane (hp disabled)
+    size_t D_bytes;
+    uint32_t *run, *off;                 // binned histogram areas (hp enabled)
+    int32_t fit_npw;                     // nodes per wave of the arc scan
+    int32_t xo_nb;                       // nodes per workgroup of init / crossover
+};
+
+// A multi-item launch: item i owns blocks [start[i], start[i + 1]) of a one-dimensional grid.
+struct Span {
+    const Item *items;
+    const int32_t *start;
+    int32_t count;
+};
+
+// Launch kinds; a kind's per-item block count depends only on the item's geometry.
+enum Kind : int {
+    K_INIT = 0,
+    K_FIT,
+    K_BIN,
+    K_HIST,
+    K_CLEAR,
+    K_ONE,  // one workgroup per item (selection kernels)
+    K_XO,
+    K_MUT0,  // + class index, N_DEG_CLASSES kinds
+    K_MUTL = K_MUT0 + N_DEG_CLASSES,
+    N_KINDS
+};
+int32_t kind_blocks(Kind k, const Item &it);  // host side
+size_t kind_lds(Kind k, const Item &it);       // dynamic LDS bytes the kind needs (host side)
+
+// ---- multi-item launchers (kernels.hip); `blocks` is the total over the span -------------
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
+int32_t kind_aux(Kind k, const Item &it);     // template / size argument of the kind
+hipError_t launch_kind(Kind k, const Span &sp, int32_t blocks, size_t lds, int32_t aux,
+                       hipStream_t s);
 hipError_t launch_extract(int32_t n, int32_t ld, int32_t pop, const int32_t *pool,
                           const int32_t *q, const int32_t *ids, int32_t k, int32_t *out,
                           hipStream_t s);
@@ -118,5 +147,9 @@ hipError_t launch_transpose_in(const int32_t *rows, int32_t n, int32_t n_ind, in
 hipError_t launch_finalize(int64_t m2, int32_t n_ind, const unsigned long long *A,
                            const unsigned long long *S, double *f1, double *f2,
                            hipStream_t s);
+
+// which selection kernel a K_ONE launch runs
+enum OneKernel : int { ONE_INIT_STATE = 0, ONE_RANK_PARENTS, ONE_SELECT, ONE_FINAL, ONE_ZERO_ACC };
+hipError_t launch_one(OneKernel which, const Span &sp, int32_t count, hipStream_t s);
 
 }  // namespace hpm

@@ -18,7 +18,7 @@ namespace hpm {
 struct FastDiv {
     uint32_t d, m, s;
     FastDiv() = default;
-    explicit FastDiv(uint32_t div) : d(div)
+    __host__ __device__ explicit FastDiv(uint32_t div) : d(div)
     {
         s = 0;
         while ((1ull << s) < div) ++s;
@@ -68,6 +68,24 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// The item that owns this workgroup in a multi-item launch, with the workgroup's index
+// among the item's blocks and the item's block count (all wave-uniform).
+__device__ __forceinline__ int item_of(const Span &sp, int &lb, int &nblk)
+{
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = sp.count;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (sp.start[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    lb = b - sp.start[lo];
+    nblk = sp.start[lo + 1] - sp.start[lo];
+    return lo;
+}
+
 __device__ __forceinline__ double f1_of(int64_t k1, int64_t m2) { return (double)k1 / (double)m2; }
 __device__ __forceinline__ double f2_of(int64_t k2, int64_t m2)
 {
@@ -103,10 +121,15 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s)
 // ---------------------------------------------------------------------------------------
 constexpr int NODE_BLOCK = 32;  // nodes per workgroup in the init kernel
 
-__global__ __launch_bounds__(256) void k_init(DevGraph g, GaConst c, int32_t *__restrict__ Q,
-                                              FastDiv divpop)
+__global__ __launch_bounds__(256) void k_init(Span sp)
 {
-    const int64_t v0 = (int64_t)blockIdx.x * NODE_BLOCK;
+    int lb, nblk;
+    const Item &it = sp.items[item_of(sp, lb, nblk)];
+    const DevGraph g = it.g;
+    const GaConst c = it.c;
+    int32_t *__restrict__ Q = const_cast<int32_t *>(it.q_cur);
+    const FastDiv divpop((uint32_t)c.pop);
+    const int64_t v0 = (int64_t)lb * NODE_BLOCK;
     const int nv = (int)min((int64_t)NODE_BLOCK, (int64_t)g.n - v0);
     const uint32_t items = (uint32_t)nv * (uint32_t)c.pop;
     for (uint32_t f = threadIdx.x; f < items; f += blockDim.x) {
@@ -119,13 +142,6 @@ __global__ __launch_bounds__(256) void k_init(DevGraph g, GaConst c, int32_t *__
         const uint32_t k = pick(w.a, d + 1u);
         Q[(size_t)v * c.ld + j] = (k == d) ? v : g.col[rs + (int32_t)k];
     }
-}
-
-hipError_t launch_init(const DevGraph &g, const GaConst &c, int32_t *Q, hipStream_t s)
-{
-    const unsigned blocks = (unsigned)((g.n + NODE_BLOCK - 1) / NODE_BLOCK);
-    k_init<<<blocks, 256, 0, s>>>(g, c, Q, FastDiv((uint32_t)c.pop));
-    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
@@ -153,15 +169,20 @@ __device__ __forceinline__ unsigned long long sq_step(int old, int d)
 // for 8 nodes at a time. Keeping the histogram atomics out of phase 1 matters: vector
 // memory counters drain in order, so an atomic issued between two gathers would make the
 // second wait for the atomic's round trip.
-__global__ __launch_bounds__(256) void k_fitness(DevGraph g, const int32_t *__restrict__ lab,
-                                                 int32_t ld, int32_t pop, int32_t nchunks,
-                                                 int32_t npw, int32_t *__restrict__ D,
-                                                 unsigned long long *__restrict__ A,
-                                                 unsigned long long *__restrict__ S,
-                                                 int32_t atomics_phase)
+__global__ __launch_bounds__(256) void k_fitness(Span sp)
 {
+    int lb, nblk;
+    const Item &it = sp.items[item_of(sp, lb, nblk)];
+    const DevGraph g = it.g;
+    const int32_t *__restrict__ lab = it.lab;
+    const int32_t ld = it.fit_ld, pop = it.fit_pop, npw = it.fit_npw;
+    const int nchunks = (pop + 127) / 128;
+    int32_t *__restrict__ D = it.D;
+    unsigned long long *__restrict__ A = it.fit_A;
+    unsigned long long *__restrict__ S = it.fit_S;
+    const int atomics_phase = it.hp.enabled ? 0 : 1;
     const int lane = lane_id();
-    const int wave = __builtin_amdgcn_readfirstlane((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+    const int wave = lb * 4 + (int)(threadIdx.x >> 6);
     const int chunk = wave % nchunks;
     const int32_t v0 = (int32_t)min((int64_t)(wave / nchunks) * npw, (int64_t)g.n);
     if (v0 >= g.n) return;
@@ -248,7 +269,7 @@ __global__ __launch_bounds__(256) void k_fitness(DevGraph g, const int32_t *__re
 //   chunk into an LDS histogram of 2^rbits counters and adds sum D_c^2 to S.
 // Every addition happens in LDS; the only global atomic is one per pass-2 workgroup.
 // ---------------------------------------------------------------------------------------
-HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg)
+HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2)
 {
     HistPlan p;
     int rb = 0;
@@ -264,7 +285,7 @@ HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg)
     // the plain histogram's n * pop global atomics are cheap for small problems, where the
     // two extra launches would cost more than they save
     p.enabled = nb >= 64 && (int64_t)max_deg < ((int64_t)1 << (32 - rb)) &&
-                (int64_t)n * pop >= ((int64_t)1 << 20);
+                (int64_t)n * pop >= ((int64_t)1 << min_log2);
     if (!p.enabled) return p;
     p.nchunks = (n + nb - 1) / nb;
     p.ngroups = (pop + HB_CG - 1) / HB_CG;
@@ -297,17 +318,22 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *w
 
 constexpr int BIN_UNROLL = 16;
 
-__global__ __launch_bounds__(256) void k_bin(DevGraph g, const int32_t *__restrict__ lab,
-                                             int32_t ld, int32_t pop, HistPlan p,
-                                             uint32_t *__restrict__ run,
-                                             uint32_t *__restrict__ off)
+__global__ __launch_bounds__(256) void k_bin(Span sp)
 {
+    int lb, nblk;
+    const Item &it = sp.items[item_of(sp, lb, nblk)];
+    const DevGraph g = it.g;
+    const int32_t *__restrict__ lab = it.lab;
+    const int32_t ld = it.fit_ld, pop = it.fit_pop;
+    const HistPlan p = it.hp;
+    uint32_t *__restrict__ run = it.run;
+    uint32_t *__restrict__ off = it.off;
     extern __shared__ uint32_t bl[];
     const int counters = p.tiles * HB_CG;
     uint32_t *cnt = bl;                             // [counters + 1]
     uint32_t *stage = bl + counters + 1;            // [nb * 16]
     uint32_t *wsum = stage + (size_t)p.nb * HB_CG;  // [4]
-    const int chunk = blockIdx.x, grp = blockIdx.y;
+    const int chunk = lb % p.nchunks, grp = lb / p.nchunks;
     const int32_t v0 = chunk * p.nb;
     const int nv = min(p.nb, g.n - v0);
     const int cg = min(HB_CG, pop - grp * HB_CG);
@@ -378,12 +404,16 @@ __global__ __launch_bounds__(256) void k_bin(DevGraph g, const int32_t *__restri
 
 constexpr int HIST_UNROLL = 8;
 
-__global__ __launch_bounds__(256) void k_hist(HistPlan p, const uint32_t *__restrict__ run,
-                                              const uint32_t *__restrict__ off,
-                                              unsigned long long *__restrict__ S)
+__global__ __launch_bounds__(256) void k_hist(Span sp)
 {
+    int lb, nblk;
+    const Item &it = sp.items[item_of(sp, lb, nblk)];
+    const HistPlan p = it.hp;
+    const uint32_t *__restrict__ run = it.run;
+    const uint32_t *__restrict__ off = it.off;
+    unsigned long long *__restrict__ S = it.fit_S;
     extern __shared__ uint32_t hist[];  // [2^rbits], the whole 64 KB at most
-    const int t = blockIdx.x, j = blockIdx.y;
+    const int t = lb % p.tiles, j = lb / p.tiles;
     const int grp = j / HB_CG, jl = j % HB_CG;
     const int counters = p.tiles * HB_CG;
     const int bucket = t * HB_CG + jl;
@@ -431,28 +461,15 @@ __global__ __launch_bounds__(256) void k_hist(HistPlan p, const uint32_t *__rest
     if (lane_id() == 0 && sq != 0) atomicAdd(S + j, sq);  // one atomic per wave
 }
 
-hipError_t launch_fitness(const DevGraph &g, const int32_t *lab, int32_t ld, int32_t pop,
-                          const HistPlan &plan, uint32_t *run, uint32_t *off, int32_t *D,
-                          unsigned long long *A, unsigned long long *S, hipStream_t s)
+// clears the plain histogram plane of every item (write-only stream)
+__global__ __launch_bounds__(256) void k_clear(Span sp)
 {
-    const int nchunks = (pop + 127) / 128;
-    // nodes per wave: long runs for streaming the CSR, but at least ~16k waves in flight
-    int npw = g.n / 16384;
-    npw = npw < 1 ? 1 : (npw > 64 ? 64 : npw);
-    const int64_t waves = ((int64_t)g.n + npw - 1) / npw * nchunks;
-    const unsigned blocks = (unsigned)((waves + 3) / 4);
-    k_fitness<<<blocks, 256, 0, s>>>(g, lab, ld, pop, nchunks, npw, D, A, S,
-                                     plan.enabled ? 0 : 1);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !plan.enabled) return e;
-    const int counters = plan.tiles * HB_CG;
-    const size_t lds1 = sizeof(uint32_t) * ((size_t)counters + 1 + (size_t)plan.nb * HB_CG + 4);
-    k_bin<<<dim3((unsigned)plan.nchunks, (unsigned)plan.ngroups), 256, lds1, s>>>(g, lab, ld, pop,
-                                                                                 plan, run, off);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const size_t lds2 = sizeof(uint32_t) * ((size_t)1 << plan.rbits);
-    k_hist<<<dim3((unsigned)plan.tiles, (unsigned)pop), 256, lds2, s>>>(plan, run, off, S);
-    return hipGetLastError();
+    int lb, nblk;
+    const Item &it = sp.items[item_of(sp, lb, nblk)];
+    uint4 *p = (uint4 *)it.D;
+    const size_t n16 = it.D_bytes / 16;
+    for (size_t i = (size_t)lb * blockDim.x + threadIdx.x; i < n16; i += (size_t)nblk * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -602,8 +619,13 @@ __device__ void rank_crowd_order(int N, int64_t m2, SelSmem &sh)
     __syncthreads();
 }
 
-__global__ __launch_bounds__(SEL_THREADS) void k_init_state(GaConst c, int64_t m2, DevState st)
+// The selection kernels run one workgroup per item: block b serves item b.
+__global__ __launch_bounds__(SEL_THREADS) void k_init_state(Span sp)
 {
+    const Item &it = sp.items[blockIdx.x];
+    const GaConst c = it.c;
+    const DevState st = it.st;
+    const int64_t m2 = it.g.m2;
     const int i = threadIdx.x;
     if (i < c.pop) {
         const int64_t A = (int64_t)st.Aq[i], S = (int64_t)st.Sq[i];
@@ -616,17 +638,15 @@ __global__ __launch_bounds__(SEL_THREADS) void k_init_state(GaConst c, int64_t m
     if (i == 0) *st.gen = 1;
 }
 
-hipError_t launch_init_state(const GaConst &c, int64_t m2, const DevState &st, hipStream_t s)
-{
-    k_init_state<<<1, SEL_THREADS, 0, s>>>(c, m2, st);
-    return hipGetLastError();
-}
-
 // Start of generation g: rank, crowd and reorder P^(g-1); draw the E_S binary tournaments
 // of every offspring and its crossover gate; clear the offspring fitness accumulators.
-__global__ __launch_bounds__(SEL_THREADS) void k_rank_parents(GaConst c, int64_t m2, DevState st)
+__global__ __launch_bounds__(SEL_THREADS) void k_rank_parents(Span sp)
 {
     __shared__ SelSmem sh;
+    const Item &it = sp.items[blockIdx.x];
+    const GaConst c = it.c;
+    const DevState st = it.st;
+    const int64_t m2 = it.g.m2;
     const int i = threadIdx.x, N = c.pop;
     if (i < N) {
         sh.k1[i] = m2 - st.ps_A[i];
@@ -661,16 +681,14 @@ __global__ __launch_bounds__(SEL_THREADS) void k_rank_parents(GaConst c, int64_t
     }
 }
 
-hipError_t launch_rank_parents(const GaConst &c, int64_t m2, const DevState &st, hipStream_t s)
-{
-    k_rank_parents<<<1, SEL_THREADS, 0, s>>>(c, m2, st);
-    return hipGetLastError();
-}
-
 // End of generation g: R = P (reordered) ++ Q, keep the first pop in crowded order.
-__global__ __launch_bounds__(SEL_THREADS) void k_select(GaConst c, int64_t m2, DevState st)
+__global__ __launch_bounds__(SEL_THREADS) void k_select(Span sp)
 {
     __shared__ SelSmem sh;
+    const Item &it = sp.items[blockIdx.x];
+    const GaConst c = it.c;
+    const DevState st = it.st;
+    const int64_t m2 = it.g.m2;
     const int i = threadIdx.x, np = c.pop, N = 2 * c.pop;
     if (i < np) {
         sh.k1[i] = m2 - st.pos_A[i];
@@ -694,16 +712,14 @@ __global__ __launch_bounds__(SEL_THREADS) void k_select(GaConst c, int64_t m2, D
     if (i == 0) *st.gen += 1;
 }
 
-hipError_t launch_select(const GaConst &c, int64_t m2, const DevState &st, hipStream_t s)
-{
-    k_select<<<1, SEL_THREADS, 0, s>>>(c, m2, st);
-    return hipGetLastError();
-}
-
 // Phase 4 of Alg. 1: the rank-1 members of the final population in crowded order.
-__global__ __launch_bounds__(SEL_THREADS) void k_final(GaConst c, int64_t m2, DevState st)
+__global__ __launch_bounds__(SEL_THREADS) void k_final(Span sp)
 {
     __shared__ SelSmem sh;
+    const Item &it = sp.items[blockIdx.x];
+    const GaConst c = it.c;
+    const DevState st = it.st;
+    const int64_t m2 = it.g.m2;
     const int i = threadIdx.x, N = c.pop;
     if (i < N) {
         sh.k1[i] = m2 - st.ps_A[i];
@@ -729,9 +745,26 @@ __global__ __launch_bounds__(SEL_THREADS) void k_final(GaConst c, int64_t m2, De
     }
 }
 
-hipError_t launch_final(const GaConst &c, int64_t m2, const DevState &st, hipStream_t s)
+// Clears the offspring accumulators before the initial population's evaluation.
+__global__ __launch_bounds__(SEL_THREADS) void k_zero_acc(Span sp)
 {
-    k_final<<<1, SEL_THREADS, 0, s>>>(c, m2, st);
+    const Item &it = sp.items[blockIdx.x];
+    for (int i = threadIdx.x; i < it.fit_pop; i += blockDim.x) {
+        it.fit_A[i] = 0ull;
+        it.fit_S[i] = 0ull;
+    }
+}
+
+hipError_t launch_one(OneKernel which, const Span &sp, int32_t count, hipStream_t s)
+{
+    if (count <= 0) return hipSuccess;
+    switch (which) {
+    case ONE_ZERO_ACC: k_zero_acc<<<count, SEL_THREADS, 0, s>>>(sp); break;
+    case ONE_INIT_STATE: k_init_state<<<count, SEL_THREADS, 0, s>>>(sp); break;
+    case ONE_RANK_PARENTS: k_rank_parents<<<count, SEL_THREADS, 0, s>>>(sp); break;
+    case ONE_SELECT: k_select<<<count, SEL_THREADS, 0, s>>>(sp); break;
+    default: k_final<<<count, SEL_THREADS, 0, s>>>(sp); break;
+    }
     return hipGetLastError();
 }
 
@@ -786,14 +819,19 @@ __device__ __forceinline__ int ensemble_plurality(const int (&L)[ES], uint64_t s
 }
 
 template <int ES>
-__global__ __launch_bounds__(256) void k_crossover(int32_t n, int32_t nblock, GaConst c,
-                                                   DevState st,
-                                                   const int32_t *__restrict__ pool_cur,
-                                                   const int32_t *__restrict__ q_cur,
-                                                   int32_t *__restrict__ pool_new,
-                                                   int32_t *__restrict__ C,
-                                                   int32_t *__restrict__ q_next, FastDiv divpop)
+__global__ __launch_bounds__(256) void k_crossover(Span sp)
 {
+    int lb, nblk;
+    const Item &it = sp.items[item_of(sp, lb, nblk)];
+    const int32_t n = it.g.n, nblock = it.xo_nb;
+    const GaConst c = it.c;
+    const DevState st = it.st;
+    const int32_t *__restrict__ pool_cur = it.pool_cur;
+    const int32_t *__restrict__ q_cur = it.q_cur;
+    int32_t *__restrict__ pool_new = it.pool_new;
+    int32_t *__restrict__ C = it.C;
+    int32_t *__restrict__ q_next = it.q_next;
+    const FastDiv divpop((uint32_t)c.pop);
     extern __shared__ int xs[];  // [pop] pos_id, [pop] gate, [pop * ES] par_id
     const int pop = c.pop, ld = c.ld;
     int *s_pos = xs, *s_gate = xs + pop, *s_par = xs + 2 * pop;
@@ -804,7 +842,7 @@ __global__ __launch_bounds__(256) void k_crossover(int32_t n, int32_t nblock, Ga
     for (int t = threadIdx.x; t < pop * ES; t += blockDim.x) s_par[t] = st.par_id[t];
     __syncthreads();
     const uint32_t g = (uint32_t)*st.gen;
-    const int64_t v0 = (int64_t)blockIdx.x * nblock;
+    const int64_t v0 = (int64_t)lb * nblock;
     const int nv = (int)min((int64_t)nblock, (int64_t)n - v0);
     const uint32_t items = (uint32_t)nv * (uint32_t)pop;
     // XO_ITEMS (node, offspring) items per thread at once: all their loads are issued
@@ -846,35 +884,6 @@ __global__ __launch_bounds__(256) void k_crossover(int32_t n, int32_t nblock, Ga
             q_next[row[t] + jj[t]] = out;
         }
     }
-}
-
-// nodes per workgroup in the per-(node, offspring) kernels: 32 for large graphs, fewer so
-// that small graphs still spread over the chip
-static int node_block(int32_t n)
-{
-    int nb = n / 2048;
-    return nb < 1 ? 1 : (nb > 32 ? 32 : nb);
-}
-
-hipError_t launch_crossover(const DevGraph &g, const GaConst &c, const DevState &st,
-                            const int32_t *pool_cur, const int32_t *q_cur, int32_t *pool_new,
-                            int32_t *C, int32_t *q_next, hipStream_t s)
-{
-    const int nb = node_block(g.n);
-    const unsigned blocks = (unsigned)((g.n + nb - 1) / nb);
-    const size_t smem = sizeof(int) * (size_t)c.pop * (size_t)(2 + c.es);
-    const FastDiv fd((uint32_t)c.pop);
-#define HPM_XO(ES_)                                                                          \
-    case ES_:                                                                                \
-        k_crossover<ES_><<<blocks, 256, smem, s>>>(g.n, nb, c, st, pool_cur, q_cur, pool_new, \
-                                                   C, q_next, fd);                           \
-        break;
-    switch (c.es) {
-        HPM_XO(1) HPM_XO(2) HPM_XO(3) HPM_XO(4) HPM_XO(5) HPM_XO(6) HPM_XO(7) HPM_XO(8)
-    default: return hipErrorInvalidValue;
-    }
-#undef HPM_XO
-    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
@@ -952,19 +961,25 @@ constexpr int MUT_LIST_CAP = 1024;  // mutation items one wave can queue (group 
 // that mutate in LDS, then resolves them one per lane. For KMAX == 16 the register array
 // size is picked per batch (4, 8 or 16) from the batch's largest degree.
 template <int KMAX, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_mutate_lanes(DevGraph g, GaConst c, DevState st,
-                                                             const int32_t *__restrict__ list,
-                                                             int32_t count_nodes,
-                                                             const int32_t *__restrict__ C,
-                                                             int32_t *__restrict__ q_next,
-                                                             FastDiv divpop)
+__global__ __launch_bounds__(64 * WAVES) void k_mutate_lanes(Span sp, int cls)
 {
+    int lb, nblk;
+    const Item &it = sp.items[item_of(sp, lb, nblk)];
+    const DevGraph g = it.g;
+    const GaConst c = it.c;
+    const DevState st = it.st;
+    const int32_t *__restrict__ C = it.C;
+    int32_t *__restrict__ q_next = it.q_next;
+    const int32_t cstart = cls == 0 ? 0 : g.class_end[cls - 1];
+    const int32_t *__restrict__ list = g.small_nodes + cstart;
+    const int32_t count_nodes = g.class_end[cls] - cstart;
+    const FastDiv divpop((uint32_t)c.pop);
     __shared__ uint2 items[WAVES][MUT_LIST_CAP];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const uint32_t gen = (uint32_t)*st.gen;
     const int pop = c.pop, G = c.mut_group;
     const int ngroups = (count_nodes + G - 1) / G;
-    for (int grp = blockIdx.x * WAVES + wv; grp < ngroups; grp += gridDim.x * WAVES) {
+    for (int grp = lb * WAVES + wv; grp < ngroups; grp += nblk * WAVES) {
         const int base = grp * G;
         const int gn = min(G, count_nodes - base);
         const uint32_t total = (uint32_t)gn * (uint32_t)pop;
@@ -1120,17 +1135,23 @@ __device__ __forceinline__ int wave_plurality(const int32_t *__restrict__ C, int
 // Degree class (64(E/2), 64E]: a wave per node draws the MUT words of all offspring, queues
 // the mutating ones in LDS and resolves them one at a time with the wave sort.
 template <int E>
-__global__ __launch_bounds__(256) void k_mutate_wave(DevGraph g, GaConst c, DevState st,
-                                                     const int32_t *__restrict__ list,
-                                                     int32_t count_nodes,
-                                                     const int32_t *__restrict__ C,
-                                                     int32_t *__restrict__ q_next)
+__global__ __launch_bounds__(256) void k_mutate_wave(Span sp, int cls)
 {
+    int lb, nblk;
+    const Item &it = sp.items[item_of(sp, lb, nblk)];
+    const DevGraph g = it.g;
+    const GaConst c = it.c;
+    const DevState st = it.st;
+    const int32_t *__restrict__ C = it.C;
+    int32_t *__restrict__ q_next = it.q_next;
+    const int32_t cstart = cls == 0 ? 0 : g.class_end[cls - 1];
+    const int32_t *__restrict__ list = g.small_nodes + cstart;
+    const int32_t count_nodes = g.class_end[cls] - cstart;
     __shared__ uint2 items[MUT_WAVES][HPMOCD_MAX_POP_DEV];
     const int wv = threadIdx.x >> 6, lane = lane_id();
     const uint32_t gen = (uint32_t)*st.gen;
     const int pop = c.pop, ld = c.ld;
-    for (int t = blockIdx.x * MUT_WAVES + wv; t < count_nodes; t += gridDim.x * MUT_WAVES) {
+    for (int t = lb * MUT_WAVES + wv; t < count_nodes; t += nblk * MUT_WAVES) {
         const int32_t node = list[t];
         const int32_t rs = g.row_ptr[node];
         const int d = g.row_ptr[node + 1] - rs;
@@ -1254,10 +1275,15 @@ __device__ int scan_plurality(const int32_t *__restrict__ C, int ld, int j,
     return prev;  // not reached
 }
 
-__global__ __launch_bounds__(128) void k_mutate_large(DevGraph g, GaConst c, DevState st,
-                                                      const int32_t *__restrict__ C,
-                                                      int32_t *__restrict__ q_next, int pmax)
+__global__ __launch_bounds__(128) void k_mutate_large(Span sp, int pmax)
 {
+    int lb, nblk;
+    const Item &it = sp.items[item_of(sp, lb, nblk)];
+    const DevGraph g = it.g;
+    const GaConst c = it.c;
+    const DevState st = it.st;
+    const int32_t *__restrict__ C = it.C;
+    int32_t *__restrict__ q_next = it.q_next;
     extern __shared__ int lds[];
     uint2 *items = (uint2 *)lds;                    // [pop]
     int *res = lds + 2 * HPMOCD_MAX_POP_DEV;        // [MUT_WAVES]
@@ -1267,7 +1293,7 @@ __global__ __launch_bounds__(128) void k_mutate_large(DevGraph g, GaConst c, Dev
     int *buf = cnt_sh + 4 + wv * pmax;              // [pmax] per wave
     const uint32_t gen = (uint32_t)*st.gen;
     const int pop = c.pop, ld = c.ld;
-    for (int t = blockIdx.x; t < g.n_large; t += gridDim.x) {
+    for (int t = lb; t < g.n_large; t += nblk) {
         const int32_t node = g.large_nodes[t];
         const int32_t rs = g.row_ptr[node];
         const int d = g.row_ptr[node + 1] - rs;
@@ -1313,55 +1339,6 @@ __global__ __launch_bounds__(128) void k_mutate_large(DevGraph g, GaConst c, Dev
         }
         __syncthreads();
     }
-}
-
-hipError_t launch_mutation(const DevGraph &g, const GaConst &c, const DevState &st,
-                           const int32_t *C, int32_t *q_next, hipStream_t s)
-{
-    if (c.thr_m == 0) return hipSuccess;  // no node can mutate
-    const FastDiv fd((uint32_t)c.pop);
-    int start = 0;
-    for (int k = 0; k < N_DEG_CLASSES; ++k) {
-        const int end = g.class_end[k];
-        const int cnt = end - start;
-        const int32_t *list = g.small_nodes + start;
-        start = end;
-        if (cnt <= 0) continue;
-        const int cls = DEG_CLASS_MAX[k];
-        if (cls <= 32) {
-            const int ngroups = (cnt + c.mut_group - 1) / c.mut_group;
-            int b = (ngroups + MUT_WAVES - 1) / MUT_WAVES;
-            const unsigned blocks = (unsigned)(b > 8192 ? 8192 : b);
-            if (cls == 16)
-                k_mutate_lanes<16, MUT_WAVES><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next, fd);
-            else
-                k_mutate_lanes<32, MUT_WAVES><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next, fd);
-        } else {
-            int b = (cnt + MUT_WAVES - 1) / MUT_WAVES;
-            const unsigned blocks = (unsigned)(b > 16384 ? 16384 : b);
-            switch (cls) {
-            case 64: k_mutate_wave<1><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
-            case 128: k_mutate_wave<2><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
-            case 256: k_mutate_wave<4><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
-            case 512: k_mutate_wave<8><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
-            case 1024: k_mutate_wave<16><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
-            default: k_mutate_wave<32><<<blocks, 256, 0, s>>>(g, c, st, list, cnt, C, q_next); break;
-            }
-        }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    if (g.n_large > 0) {
-        int pmax = 64;
-        while (pmax < g.large_max_deg && pmax < LARGE_SORT_CAP) pmax <<= 1;
-        const int waves = 2;
-        const size_t smem = sizeof(int) * (2 * (size_t)HPMOCD_MAX_POP_DEV + MUT_WAVES + 4 +
-                                           (size_t)waves * pmax);
-        const int blocks = g.n_large < 8192 ? g.n_large : 8192;
-        k_mutate_large<<<blocks, 64 * waves, smem, s>>>(g, c, st, C, q_next, pmax);
-        return hipGetLastError();
-    }
-    return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1432,6 +1409,121 @@ hipError_t launch_finalize(int64_t m2, int32_t n_ind, const unsigned long long *
                            const unsigned long long *S, double *f1, double *f2, hipStream_t s)
 {
     k_finalize<<<(unsigned)((n_ind + 255) / 256), 256, 0, s>>>(m2, n_ind, A, S, f1, f2);
+    return hipGetLastError();
+}
+
+}  // namespace hpm
+
+namespace hpm {
+
+// ---------------------------------------------------------------------------------------
+// launch geometry of every kind, per item (host side)
+// ---------------------------------------------------------------------------------------
+static int32_t ceil_div(int64_t a, int64_t b) { return (int32_t)((a + b - 1) / b); }
+
+static int32_t large_pmax(const Item &it)
+{
+    int pmax = 64;
+    while (pmax < it.g.large_max_deg && pmax < LARGE_SORT_CAP) pmax <<= 1;
+    return pmax;
+}
+
+int32_t kind_blocks(Kind k, const Item &it)
+{
+    const DevGraph &g = it.g;
+    switch (k) {
+    case K_INIT: return ceil_div(g.n, NODE_BLOCK);
+    case K_FIT: return ceil_div((int64_t)ceil_div(g.n, it.fit_npw) * ((it.fit_pop + 127) / 128), 4);
+    case K_BIN: return it.hp.enabled ? it.hp.nchunks * it.hp.ngroups : 0;
+    case K_HIST: return it.hp.enabled ? it.hp.tiles * it.fit_pop : 0;
+    case K_CLEAR: {
+        if (it.hp.enabled) return 0;
+        const int32_t b = ceil_div((int64_t)(it.D_bytes / 16), 256);
+        return b < 1 ? 1 : (b > 2048 ? 2048 : b);
+    }
+    case K_ONE: return 1;
+    case K_XO: return ceil_div(g.n, it.xo_nb);
+    case K_MUTL:
+        if (it.c.thr_m == 0 || g.n_large == 0) return 0;
+        return g.n_large < 8192 ? g.n_large : 8192;
+    default: break;
+    }
+    const int cls = (int)k - (int)K_MUT0;
+    if (cls < 0 || cls >= N_DEG_CLASSES || it.c.thr_m == 0) return 0;
+    const int32_t start = cls == 0 ? 0 : g.class_end[cls - 1];
+    const int32_t cnt = g.class_end[cls] - start;
+    if (cnt <= 0) return 0;
+    if (DEG_CLASS_MAX[cls] <= 32) {
+        const int32_t b = ceil_div(ceil_div(cnt, it.c.mut_group), MUT_WAVES);
+        return b > 8192 ? 8192 : b;
+    }
+    const int32_t b = ceil_div(cnt, MUT_WAVES);
+    return b > 16384 ? 16384 : b;
+}
+
+size_t kind_lds(Kind k, const Item &it)
+{
+    switch (k) {
+    case K_BIN:
+        return it.hp.enabled ? sizeof(uint32_t) * ((size_t)it.hp.tiles * HB_CG + 1 +
+                                                   (size_t)it.hp.nb * HB_CG + 4)
+                             : 0;
+    case K_HIST: return it.hp.enabled ? sizeof(uint32_t) * ((size_t)1 << it.hp.rbits) : 0;
+    case K_XO: return sizeof(int) * (size_t)it.c.pop * (size_t)(2 + it.c.es);
+    case K_MUTL:
+        return sizeof(int) * (2 * (size_t)HPMOCD_MAX_POP_DEV + MUT_WAVES + 4 +
+                              2 * (size_t)large_pmax(it));
+    default: return 0;
+    }
+}
+
+int32_t kind_aux(Kind k, const Item &it)
+{
+    if (k == K_XO) return it.c.es;
+    if (k == K_MUTL) return large_pmax(it);
+    return 0;
+}
+
+hipError_t launch_kind(Kind k, const Span &sp, int32_t blocks, size_t lds, int32_t aux,
+                       hipStream_t s)
+{
+    if (blocks <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)blocks;
+    switch (k) {
+    case K_INIT: k_init<<<nb, 256, 0, s>>>(sp); break;
+    case K_FIT: k_fitness<<<nb, 256, 0, s>>>(sp); break;
+    case K_BIN: k_bin<<<nb, 256, lds, s>>>(sp); break;
+    case K_HIST: k_hist<<<nb, 256, lds, s>>>(sp); break;
+    case K_CLEAR: k_clear<<<nb, 256, 0, s>>>(sp); break;
+    case K_XO:
+        switch (aux) {
+        case 1: k_crossover<1><<<nb, 256, lds, s>>>(sp); break;
+        case 2: k_crossover<2><<<nb, 256, lds, s>>>(sp); break;
+        case 3: k_crossover<3><<<nb, 256, lds, s>>>(sp); break;
+        case 4: k_crossover<4><<<nb, 256, lds, s>>>(sp); break;
+        case 5: k_crossover<5><<<nb, 256, lds, s>>>(sp); break;
+        case 6: k_crossover<6><<<nb, 256, lds, s>>>(sp); break;
+        case 7: k_crossover<7><<<nb, 256, lds, s>>>(sp); break;
+        case 8: k_crossover<8><<<nb, 256, lds, s>>>(sp); break;
+        default: return hipErrorInvalidValue;
+        }
+        break;
+    case K_MUTL: k_mutate_large<<<nb, 128, lds, s>>>(sp, aux); break;
+    default: {
+        const int cls = (int)k - (int)K_MUT0;
+        switch (cls) {
+        case 0: k_mutate_lanes<16, MUT_WAVES><<<nb, 64 * MUT_WAVES, 0, s>>>(sp, cls); break;
+        case 1: k_mutate_lanes<32, MUT_WAVES><<<nb, 64 * MUT_WAVES, 0, s>>>(sp, cls); break;
+        case 2: k_mutate_wave<1><<<nb, 64 * MUT_WAVES, 0, s>>>(sp, cls); break;
+        case 3: k_mutate_wave<2><<<nb, 64 * MUT_WAVES, 0, s>>>(sp, cls); break;
+        case 4: k_mutate_wave<4><<<nb, 64 * MUT_WAVES, 0, s>>>(sp, cls); break;
+        case 5: k_mutate_wave<8><<<nb, 64 * MUT_WAVES, 0, s>>>(sp, cls); break;
+        case 6: k_mutate_wave<16><<<nb, 64 * MUT_WAVES, 0, s>>>(sp, cls); break;
+        case 7: k_mutate_wave<32><<<nb, 64 * MUT_WAVES, 0, s>>>(sp, cls); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    }
     return hipGetLastError();
 }
 

@@ -1,0 +1,790 @@
+// Runs of Alg. 1 on the device: workspace carving, the batch runner (many populations, each
+// on its own graph, advanced together by multi-item launches), hipGraph replay of the
+// generation loop, the autotuner, tracing, front extraction and the run/eval entry points.
+// A single run is a batch of one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "host.hpp"
+#include "philox.hpp"
+#include "run.hpp"
+
+namespace hpm {
+
+size_t align_up(size_t x) { return (x + 255) / 256 * 256; }
+int32_t round16(int32_t x) { return (x + 15) / 16 * 16; }
+
+namespace {
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    template <class T>
+    T *take(size_t count)
+    {
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += align_up(sizeof(T) * count);
+        return p;
+    }
+};
+
+}  // namespace
+
+RunLayout carve_run(void *ws, int32_t n, int32_t pop, int32_t es, int32_t max_deg,
+                    int32_t hist_min_log2, bool both_histograms)
+{
+    RunLayout L;
+    L.hp = hist_plan(n, pop, max_deg, hist_min_log2);
+    L.ld = round16(pop);
+    L.plane = (size_t)n * (size_t)L.ld * sizeof(int32_t);
+    Carver cv(ws);
+    const size_t cells = (size_t)n * (size_t)L.ld;
+    L.pool[0] = cv.take<int32_t>(cells);
+    L.pool[1] = cv.take<int32_t>(cells);
+    L.q[0] = cv.take<int32_t>(cells);
+    L.q[1] = cv.take<int32_t>(cells);
+    L.C = cv.take<int32_t>(cells);
+    HistPlan widest = hist_plan(n, pop, max_deg, 0);  // the binned plan, when it applies
+    if (L.hp.enabled || (both_histograms && widest.enabled)) {
+        const HistPlan &h = L.hp.enabled ? L.hp : widest;
+        L.run = cv.take<uint32_t>(h.entries);
+        L.off = cv.take<uint32_t>(h.offsets);
+    }
+    if (!L.hp.enabled || both_histograms) L.D = cv.take<int32_t>(cells);
+    DevState &s = L.st;
+    s.gen = cv.take<int32_t>(1);
+    s.ps_id = cv.take<int32_t>(pop);
+    s.ps_A = cv.take<int64_t>(pop);
+    s.ps_S = cv.take<int64_t>(pop);
+    s.ps_f1 = cv.take<double>(pop);
+    s.ps_f2 = cv.take<double>(pop);
+    s.pos_id = cv.take<int32_t>(pop);
+    s.pos_A = cv.take<int64_t>(pop);
+    s.pos_S = cv.take<int64_t>(pop);
+    s.tr_rank = cv.take<int32_t>(pop);
+    s.tr_crowd = cv.take<double>(pop);
+    s.par_id = cv.take<int32_t>((size_t)pop * es);
+    s.gate = cv.take<int32_t>(pop);
+    s.Aq = cv.take<unsigned long long>(pop);
+    s.Sq = cv.take<unsigned long long>(pop);
+    s.fr_count = cv.take<int32_t>(1);
+    s.fr_id = cv.take<int32_t>(pop);
+    s.fr_A = cv.take<int64_t>(pop);
+    s.fr_S = cv.take<int64_t>(pop);
+    s.fr_f1 = cv.take<double>(pop);
+    s.fr_f2 = cv.take<double>(pop);
+    L.bytes = cv.off;
+    return L;
+}
+
+GaConst ga_const(const hpmocd_params *p, int32_t ld, int32_t mut_target)
+{
+    GaConst c;
+    c.pop = p->pop_size;
+    c.ld = ld;
+    c.es = p->parents_per_child;
+    c.seed = p->seed;
+    c.thr_c = bernoulli_threshold(p->crossover_p);
+    c.thr_m = bernoulli_threshold(p->mutation_p);
+    // nodes per wave group in the small-degree mutation kernels: enough candidate (node,
+    // offspring) pairs to fill about mut_target mutations, within the LDS list capacity
+    int g = 1;
+    if (p->mutation_p > 0.0) g = (int)std::ceil(mut_target / (p->pop_size * p->mutation_p));
+    g = std::max(1, std::min(g, 1024 / p->pop_size));
+    c.mut_group = g;
+    return c;
+}
+
+void Pop::setup(const hpmocd_graph *graph, const hpmocd_params &params, void *ws,
+                const Tuning &t, int64_t batch_nodes, bool both_histograms)
+{
+    G = graph;
+    p = params;
+    L = carve_run(ws, G->n, p.pop_size, p.parents_per_child, G->max_deg, t.hist_min_log2,
+                  both_histograms);
+    c = ga_const(&p, L.ld, t.mut_target_items);
+    dg = dev_graph(G);
+    const int64_t npw = batch_nodes / std::max<int64_t>(1, t.fit_target_waves);
+    fit_npw = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, npw));
+    const int64_t nb = batch_nodes / std::max<int64_t>(1, t.xo_target_blocks);
+    xo_nb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(32, nb));
+    cur = 0;
+}
+
+Item Pop::item(int which) const
+{
+    Item it{};
+    it.g = dg;
+    it.c = c;
+    it.st = L.st;
+    it.hp = L.hp;
+    it.D = L.D;
+    it.D_bytes = L.D ? L.plane : 0;
+    it.run = L.run;
+    it.off = L.off;
+    it.fit_pop = c.pop;
+    it.fit_ld = L.ld;
+    it.fit_A = L.st.Aq;
+    it.fit_S = L.st.Sq;
+    it.fit_npw = fit_npw;
+    it.xo_nb = xo_nb;
+    it.C = L.C;
+    if (which == ITEM_INIT) {
+        it.q_cur = L.q[0];
+        it.lab = L.q[0];
+        it.pool_cur = L.pool[0];
+        it.pool_new = L.pool[1];
+        it.q_next = L.q[1];
+    } else {
+        const int a = which == ITEM_PARITY0 ? 0 : 1, b = 1 - a;
+        it.pool_cur = L.pool[a];
+        it.q_cur = L.q[a];
+        it.pool_new = L.pool[b];
+        it.q_next = L.q[b];
+        it.lab = L.q[b];
+    }
+    return it;
+}
+
+size_t meta_bytes(int32_t count)
+{
+    return align_up(sizeof(Item) * (size_t)count) +
+           align_up(sizeof(int32_t) * (size_t)N_KINDS * ((size_t)count + 1));
+}
+
+int Meta::upload(const std::vector<Item> &host_items, void *region)
+{
+    count = (int32_t)host_items.size();
+    items = (Item *)region;
+    starts = (int32_t *)((char *)region + align_up(sizeof(Item) * (size_t)count));
+    std::vector<int32_t> st((size_t)N_KINDS * ((size_t)count + 1), 0);
+    for (int k = 0; k < N_KINDS; ++k) {
+        int32_t *row = st.data() + (size_t)k * (count + 1);
+        int64_t acc = 0;
+        lds[k] = 0;
+        aux[k] = 0;
+        for (int32_t i = 0; i < count; ++i) {
+            row[i] = (int32_t)acc;
+            acc += kind_blocks((Kind)k, host_items[i]);
+            lds[k] = std::max(lds[k], kind_lds((Kind)k, host_items[i]));
+            aux[k] = std::max(aux[k], kind_aux((Kind)k, host_items[i]));
+        }
+        row[count] = (int32_t)acc;
+        if (acc > 0x7fffffff) return HPMOCD_ERR_ARG;
+        totals[k] = (int32_t)acc;
+    }
+    HIP_TRY(hipMemcpy(items, host_items.data(), sizeof(Item) * (size_t)count, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(starts, st.data(), sizeof(int32_t) * st.size(), hipMemcpyHostToDevice));
+    return HPMOCD_OK;
+}
+
+hipError_t Meta::launch(Kind k, hipStream_t s) const
+{
+    return launch_kind(k, span(k), totals[k], lds[k], aux[k], s);
+}
+
+hipError_t Meta::one(OneKernel which, hipStream_t s) const
+{
+    return launch_one(which, span(K_ONE), count, s);
+}
+
+hipError_t launch_fitness_kinds(const Meta &m, hipStream_t s)
+{
+    hipError_t e;
+    if ((e = m.launch(K_FIT, s)) != hipSuccess) return e;
+    if ((e = m.launch(K_BIN, s)) != hipSuccess) return e;
+    return m.launch(K_HIST, s);
+}
+
+hipError_t launch_init_seq(const Meta &m, hipStream_t s)
+{
+    hipError_t e;
+    if ((e = m.launch(K_CLEAR, s)) != hipSuccess) return e;  // plain histograms start at zero
+    if ((e = m.one(ONE_ZERO_ACC, s)) != hipSuccess) return e;
+    if ((e = m.launch(K_INIT, s)) != hipSuccess) return e;
+    if ((e = launch_fitness_kinds(m, s)) != hipSuccess) return e;
+    if ((e = m.launch(K_CLEAR, s)) != hipSuccess) return e;
+    return m.one(ONE_INIT_STATE, s);
+}
+
+hipError_t launch_generation(const Meta &m, hipStream_t s, const EventPair *ev)
+{
+    hipError_t e;
+    auto mark = [&](int k, bool end) {
+        if (ev) (void)hipEventRecord(end ? ev[k].b : ev[k].a, s);
+    };
+    mark(0, false);
+    if ((e = m.one(ONE_RANK_PARENTS, s)) != hipSuccess) return e;
+    mark(0, true);
+    mark(1, false);
+    if ((e = m.launch(K_XO, s)) != hipSuccess) return e;
+    for (int k = 0; k < N_DEG_CLASSES; ++k)
+        if ((e = m.launch((Kind)(K_MUT0 + k), s)) != hipSuccess) return e;
+    if ((e = m.launch(K_MUTL, s)) != hipSuccess) return e;
+    mark(1, true);
+    mark(2, false);
+    if ((e = launch_fitness_kinds(m, s)) != hipSuccess) return e;
+    mark(2, true);
+    mark(3, false);
+    if ((e = m.launch(K_CLEAR, s)) != hipSuccess) return e;
+    mark(3, true);
+    mark(4, false);
+    if ((e = m.one(ONE_SELECT, s)) != hipSuccess) return e;
+    mark(4, true);
+    return hipSuccess;
+}
+
+float elapsed(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.f;
+    return ms;
+}
+
+EventSet::~EventSet()
+{
+    for (hipEvent_t e : all) (void)hipEventDestroy(e);
+}
+
+hipEvent_t EventSet::make()
+{
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    all.push_back(e);
+    return e;
+}
+
+// Host copy of one population (selection order) for the trace callback.
+int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, void *user,
+               bool with_labels)
+{
+    const int32_t n = P.G->n, pop = P.c.pop, ld = P.c.ld;
+    const RunLayout &L = P.L;
+    const int cur = P.cur;
+    const size_t plane_cells = with_labels ? (size_t)n * ld : 0;
+    std::vector<int32_t> pool(plane_cells), q(plane_cells), ids(pop), rank(pop);
+    std::vector<int64_t> A(pop), S(pop);
+    std::vector<double> f1(pop), f2(pop), crowd(pop);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (with_labels && gen > 0)
+        HIP_TRY(hipMemcpy(pool.data(), L.pool[cur], L.plane, hipMemcpyDeviceToHost));
+    if (with_labels) HIP_TRY(hipMemcpy(q.data(), L.q[cur], L.plane, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(ids.data(), L.st.ps_id, sizeof(int32_t) * pop, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(A.data(), L.st.ps_A, sizeof(int64_t) * pop, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(S.data(), L.st.ps_S, sizeof(int64_t) * pop, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(f1.data(), L.st.ps_f1, sizeof(double) * pop, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(f2.data(), L.st.ps_f2, sizeof(double) * pop, hipMemcpyDeviceToHost));
+    if (gen > 0) {
+        HIP_TRY(hipMemcpy(rank.data(), L.st.tr_rank, sizeof(int32_t) * pop, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpy(crowd.data(), L.st.tr_crowd, sizeof(double) * pop, hipMemcpyDeviceToHost));
+    }
+    std::vector<int32_t> rows(with_labels ? (size_t)pop * n : 0);
+    for (int32_t i = 0; with_labels && i < pop; ++i) {
+        const int32_t id = ids[i];
+        const int32_t *src = id < pop ? pool.data() + id : q.data() + (id - pop);
+        int32_t *dst = rows.data() + (size_t)i * n;
+        for (int32_t v = 0; v < n; ++v) dst[v] = src[(size_t)v * ld];
+    }
+    hpmocd_state_view view;
+    view.g = gen;
+    view.pop_size = pop;
+    view.n_nodes = n;
+    view.labels = with_labels ? rows.data() : nullptr;
+    view.A = A.data();
+    view.S = S.data();
+    view.f1 = f1.data();
+    view.f2 = f2.data();
+    view.rank = gen > 0 ? rank.data() : nullptr;
+    view.crowd = gen > 0 ? crowd.data() : nullptr;
+    fn(&view, user);
+    return HPMOCD_OK;
+}
+
+// Front of one population after its final ranking (k_final has run): device -> host.
+int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out)
+{
+    const RunLayout &L = P.L;
+    const int32_t n = P.G->n, pop = P.c.pop;
+    int32_t k = 0;
+    HIP_TRY(hipMemcpyAsync(&k, L.st.fr_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (k < 1 || k > pop) return HPMOCD_ERR_HIP;
+    HIP_TRY(launch_extract(n, P.c.ld, pop, L.pool[P.cur], L.q[P.cur], L.st.fr_id, k, L.C, s));
+    hpmocd_front *f = (hpmocd_front *)std::calloc(1, sizeof(hpmocd_front));
+    if (!f) return HPMOCD_ERR_NOMEM;
+    f->n_solutions = k;
+    f->n_nodes = n;
+    f->labels = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)k * n);
+    f->intra_arcs = (int64_t *)std::malloc(sizeof(int64_t) * k);
+    f->sum_deg_sq = (int64_t *)std::malloc(sizeof(int64_t) * k);
+    f->f1 = (double *)std::malloc(sizeof(double) * k);
+    f->f2 = (double *)std::malloc(sizeof(double) * k);
+    if (!f->labels || !f->intra_arcs || !f->sum_deg_sq || !f->f1 || !f->f2) {
+        hpmocd_front_free(f);
+        return HPMOCD_ERR_NOMEM;
+    }
+    bool ok = hipMemcpyAsync(f->labels, L.C, sizeof(int32_t) * (size_t)k * n, hipMemcpyDeviceToHost, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(f->intra_arcs, L.st.fr_A, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(f->sum_deg_sq, L.st.fr_S, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(f->f1, L.st.fr_f1, sizeof(double) * k, hipMemcpyDeviceToHost, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(f->f2, L.st.fr_f2, sizeof(double) * k, hipMemcpyDeviceToHost, s) == hipSuccess;
+    ok = ok && hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+        hpmocd_front_free(f);
+        return HPMOCD_ERR_HIP;
+    }
+    // Alg. 3: first maximiser of Q = (1 - f1) - f2
+    double best = -INFINITY;
+    int32_t sel = 0;
+    for (int32_t i = 0; i < k; ++i) {
+        const double qv = (1.0 - f->f1[i]) - f->f2[i];
+        if (qv > best) {
+            best = qv;
+            sel = i;
+        }
+    }
+    f->selected = sel;
+    *out = f;
+    return HPMOCD_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// Batch: the populations, their workspace and the three item tables (init, parity 0, 1).
+// ---------------------------------------------------------------------------------------
+struct BatchLayout {
+    std::vector<size_t> pop_off;  // byte offset of each population's region
+    size_t meta_off[3] = {0, 0, 0};
+    size_t bytes = 0;
+};
+
+static BatchLayout batch_layout(const hpmocd_graph *const *graphs, int32_t count,
+                                const hpmocd_params *params, const Tuning &t, bool both)
+{
+    BatchLayout B;
+    size_t off = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        B.pop_off.push_back(off);
+        off += align_up(carve_run(nullptr, graphs[i]->n, params[i].pop_size,
+                                  params[i].parents_per_child, graphs[i]->max_deg,
+                                  t.hist_min_log2, both)
+                            .bytes);
+    }
+    for (int k = 0; k < 3; ++k) {
+        B.meta_off[k] = off;
+        off += meta_bytes(count);
+    }
+    B.bytes = off;
+    return B;
+}
+
+static int check_batch(const hpmocd_graph *const *graphs, int32_t count,
+                       const hpmocd_params *params)
+{
+    if (!graphs || !params || count < 1) return HPMOCD_ERR_ARG;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!graphs[i]) return HPMOCD_ERR_ARG;
+        int rc = check_params(&params[i]);
+        if (rc) return rc;
+        // one generation count and one ensemble size per batch (shared launches)
+        if (params[i].generations != params[0].generations ||
+            params[i].parents_per_child != params[0].parents_per_child)
+            return HPMOCD_ERR_ARG;
+    }
+    return HPMOCD_OK;
+}
+
+int Batch::setup(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_params *params,
+                 void *ws, size_t ws_bytes, const Tuning &t, bool both)
+{
+    tuning = t;
+    BatchLayout B = batch_layout(graphs, count, params, t, both);
+    if (ws_bytes < B.bytes) return HPMOCD_ERR_WORKSPACE;
+    int64_t total_nodes = 0;
+    for (int32_t i = 0; i < count; ++i) total_nodes += graphs[i]->n;
+    pops.assign(count, Pop{});
+    for (int32_t i = 0; i < count; ++i)
+        pops[i].setup(graphs[i], params[i], (char *)ws + B.pop_off[i], t, total_nodes, both);
+    for (int w = 0; w < 3; ++w) {
+        std::vector<Item> items;
+        for (const Pop &P : pops) items.push_back(P.item(w == 0 ? ITEM_INIT : (w == 1 ? ITEM_PARITY0 : ITEM_PARITY1)));
+        int rc = meta[w].upload(items, (char *)ws + B.meta_off[w]);
+        if (rc) return rc;
+    }
+    return HPMOCD_OK;
+}
+
+// Runs generations [first, last] of every population. Uses hipGraph replay of the
+// two-generation parity cycle when allowed; otherwise launches kernels one by one.
+int Batch::generations(int32_t first, int32_t last, hipStream_t s, bool use_graph,
+                       std::vector<std::vector<EventPair>> *ev, hpmocd_trace_fn trace,
+                       void *user, bool trace_labels)
+{
+    int32_t gen = first;
+    if (use_graph && last - first + 1 >= 2 && !trace && !ev) {
+        const int p0 = pops.empty() ? 0 : pops[0].cur;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        hipError_t e1 = launch_generation(meta[1 + p0], s, nullptr);
+        hipError_t e2 = e1 == hipSuccess ? launch_generation(meta[1 + (1 - p0)], s, nullptr) : e1;
+        hipError_t ec = hipStreamEndCapture(s, &graph);
+        if (e1 != hipSuccess || e2 != hipSuccess || ec != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return HPMOCD_ERR_HIP;
+        }
+        hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return HPMOCD_ERR_HIP;
+        const int32_t pairs = (last - first + 1) / 2;
+        hipError_t el = hipSuccess;
+        for (int32_t k = 0; k < pairs && el == hipSuccess; ++k) el = hipGraphLaunch(exec, s);
+        (void)hipGraphExecDestroy(exec);
+        if (el != hipSuccess) return HPMOCD_ERR_HIP;
+        gen += 2 * pairs;
+    }
+    for (; gen <= last; ++gen) {
+        const int par = pops.empty() ? 0 : pops[0].cur;
+        const EventPair *evp = ev ? (*ev)[(size_t)(gen - 1)].data() : nullptr;
+        HIP_TRY(launch_generation(meta[1 + par], s, evp));
+        for (Pop &P : pops) P.cur = 1 - P.cur;
+        if (trace) {
+            int rc = emit_state(pops[0], gen, s, trace, user, trace_labels);
+            if (rc) return rc;
+        }
+    }
+    // after a graph replay every population has advanced an even number of generations,
+    // so its parity is unchanged
+    return HPMOCD_OK;
+}
+
+// Autotuner: coordinate descent over the launch-shape knobs, each candidate timed on the
+// initial population plus two generations of this very batch (results discarded; every
+// choice gives identical results, only the work decomposition changes).
+static int autotune(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_params *params,
+                    void *ws, size_t ws_bytes, hipStream_t s, Tuning *best, double *probe_ms)
+{
+    std::vector<hpmocd_params> probe(params, params + count);
+    for (auto &p : probe) p.generations = 2;
+    EventSet evs;
+    hipEvent_t a = evs.make(), b = evs.make();
+    if (!a || !b) return HPMOCD_ERR_HIP;
+    auto time_it = [&](const Tuning &t, double *ms) -> int {
+        Batch bt;
+        int rc = bt.setup(graphs, count, probe.data(), ws, ws_bytes, t, true);
+        if (rc) return rc;
+        HIP_TRY(launch_init_seq(bt.meta[0], s));
+        HIP_TRY(hipEventRecord(a, s));
+        rc = bt.generations(1, 2, s, false, nullptr, nullptr, nullptr, false);
+        if (rc) return rc;
+        HIP_TRY(hipEventRecord(b, s));
+        HIP_TRY(hipEventSynchronize(b));
+        *ms = elapsed(a, b);
+        return HPMOCD_OK;
+    };
+    Tuning cur = *best;
+    double cur_ms = 0;
+    int rc = time_it(cur, &cur_ms);
+    if (rc) return rc;
+    double spent = cur_ms;
+    const int32_t fit_c[] = {2048, 8192, 16384, 65536};
+    const int32_t xo_c[] = {512, 2048, 8192};
+    const int32_t mut_c[] = {48, 96, 192};
+    const int32_t hist_c[] = {16, 20, 24, 31};
+    for (int knob = 0; knob < 4; ++knob) {
+        const int32_t *vals = knob == 0 ? fit_c : knob == 1 ? xo_c : knob == 2 ? mut_c : hist_c;
+        const int nv = knob == 0 ? 4 : knob == 3 ? 4 : 3;
+        for (int i = 0; i < nv; ++i) {
+            Tuning t = cur;
+            int32_t *field = knob == 0 ? &t.fit_target_waves : knob == 1 ? &t.xo_target_blocks
+                             : knob == 2 ? &t.mut_target_items : &t.hist_min_log2;
+            if (*field == vals[i]) continue;
+            *field = vals[i];
+            double ms = 0;
+            if ((rc = time_it(t, &ms))) return rc;
+            spent += ms;
+            if (ms < cur_ms) {
+                cur = t;
+                cur_ms = ms;
+            }
+        }
+    }
+    *best = cur;
+    if (probe_ms) *probe_ms = spent;
+    return HPMOCD_OK;
+}
+
+int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_params *params,
+              void *ws, size_t ws_bytes, void *stream, int flags, hpmocd_profile *prof,
+              hpmocd_trace_fn trace, void *user, hpmocd_front **outs)
+{
+    int rc = check_batch(graphs, count, params);
+    if (rc) return rc;
+    if (!ws || !outs) return HPMOCD_ERR_ARG;
+    if (trace && count != 1) return HPMOCD_ERR_ARG;
+    for (int32_t i = 0; i < count; ++i)
+        if ((rc = check_device(graphs[i]))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t T = params[0].generations;
+    const bool autotune_on = (flags & HPMOCD_AUTOTUNE) != 0;
+    Tuning t;
+    double probe_ms = 0;
+    if (autotune_on && (rc = autotune(graphs, count, params, ws, ws_bytes, s, &t, &probe_ms)))
+        return rc;
+    Batch B;
+    if ((rc = B.setup(graphs, count, params, ws, ws_bytes, t, autotune_on))) return rc;
+    const bool time_kernels = (flags & HPMOCD_TIME_KERNELS) != 0 && prof;
+    const bool trace_labels = (flags & HPMOCD_TRACE_NO_LABELS) == 0;
+    const bool use_graph = !(flags & (HPMOCD_NO_GRAPH | HPMOCD_TIME_KERNELS)) && !trace &&
+                           s != nullptr;
+
+    EventSet evs;
+    std::vector<std::vector<EventPair>> gen_events;
+    if (time_kernels) {
+        gen_events.assign((size_t)T, std::vector<EventPair>(5));
+        for (auto &v : gen_events)
+            for (auto &pr : v) {
+                pr.a = evs.make();
+                pr.b = evs.make();
+                if (!pr.a || !pr.b) return HPMOCD_ERR_HIP;
+            }
+    }
+    hipEvent_t e_start = nullptr, e_loop0 = nullptr, e_loop1 = nullptr, e_end = nullptr;
+    hipEvent_t e_fit0 = nullptr, e_fit1 = nullptr;
+    if (prof) {
+        e_start = evs.make();
+        e_loop0 = evs.make();
+        e_loop1 = evs.make();
+        e_end = evs.make();
+        e_fit0 = evs.make();
+        e_fit1 = evs.make();
+        if (!e_start || !e_loop0 || !e_loop1 || !e_end || !e_fit0 || !e_fit1) return HPMOCD_ERR_HIP;
+        HIP_TRY(hipEventRecord(e_start, s));
+    }
+    // initial populations (Alg. 1 phases 1-2)
+    const Meta &mi = B.meta[0];
+    HIP_TRY(mi.launch(K_CLEAR, s));
+    HIP_TRY(mi.one(ONE_ZERO_ACC, s));
+    HIP_TRY(mi.launch(K_INIT, s));
+    if (prof) HIP_TRY(hipEventRecord(e_fit0, s));
+    HIP_TRY(launch_fitness_kinds(mi, s));
+    if (prof) HIP_TRY(hipEventRecord(e_fit1, s));
+    HIP_TRY(mi.launch(K_CLEAR, s));
+    HIP_TRY(mi.one(ONE_INIT_STATE, s));
+    if (trace && (rc = emit_state(B.pops[0], 0, s, trace, user, trace_labels))) return rc;
+
+    if (prof) HIP_TRY(hipEventRecord(e_loop0, s));
+    if ((rc = B.generations(1, T, s, use_graph, time_kernels ? &gen_events : nullptr, trace, user,
+                            trace_labels)))
+        return rc;
+    if (prof) HIP_TRY(hipEventRecord(e_loop1, s));
+
+    // phase 4: first front of every population
+    HIP_TRY(B.meta[1].one(ONE_FINAL, s));
+    for (int32_t i = 0; i < count; ++i) outs[i] = nullptr;
+    for (int32_t i = 0; i < count; ++i) {
+        if ((rc = extract_front(B.pops[i], s, &outs[i]))) {
+            for (int32_t j = 0; j < i; ++j) {
+                hpmocd_front_free(outs[j]);
+                outs[j] = nullptr;
+            }
+            return rc;
+        }
+    }
+    if (prof) {
+        HIP_TRY(hipEventRecord(e_end, s));
+        HIP_TRY(hipEventSynchronize(e_end));
+        double fit_ms = 0, sweep_ms = 0, var_ms = 0, sel_ms = 0;
+        for (auto &ev : gen_events) {
+            sel_ms += elapsed(ev[0].a, ev[0].b) + elapsed(ev[4].a, ev[4].b);
+            var_ms += elapsed(ev[1].a, ev[1].b);
+            fit_ms += elapsed(ev[2].a, ev[2].b);
+            sweep_ms += elapsed(ev[3].a, ev[3].b);
+        }
+        int64_t inds = 0;
+        for (const Pop &P : B.pops) inds += (int64_t)P.c.pop * ((int64_t)T + 1);
+        prof->total_ms = elapsed(e_start, e_end);
+        prof->loop_ms = elapsed(e_loop0, e_loop1);
+        prof->fitness_ms = time_kernels ? fit_ms + elapsed(e_fit0, e_fit1) : 0.0;
+        prof->sweep_ms = time_kernels ? sweep_ms : 0.0;
+        prof->variation_ms = time_kernels ? var_ms : 0.0;
+        prof->select_ms = time_kernels ? sel_ms : 0.0;
+        prof->fitness_launches = (int64_t)T + 1;
+        prof->individual_evals = inds;
+        prof->tune_fit_target_waves = B.tuning.fit_target_waves;
+        prof->tune_xo_target_blocks = B.tuning.xo_target_blocks;
+        prof->tune_mut_target_items = B.tuning.mut_target_items;
+        prof->tune_hist_min_log2 = B.tuning.hist_min_log2;
+        prof->tune_probe_ms = probe_ms;
+    }
+    return HPMOCD_OK;
+}
+
+size_t batch_workspace(const hpmocd_graph *const *graphs, int32_t count,
+                       const hpmocd_params *params, bool both)
+{
+    Tuning t;
+    return batch_layout(graphs, count, params, t, both).bytes;
+}
+
+}  // namespace hpm
+
+using namespace hpm;
+
+extern "C" {
+
+void hpmocd_front_free(hpmocd_front *f)
+{
+    if (!f) return;
+    std::free(f->labels);
+    std::free(f->intra_arcs);
+    std::free(f->sum_deg_sq);
+    std::free(f->f1);
+    std::free(f->f2);
+    std::free(f);
+}
+
+int hpmocd_workspace_size(const hpmocd_graph *g, const hpmocd_params *p, size_t *bytes)
+{
+    if (!g || !bytes) return HPMOCD_ERR_ARG;
+    int rc = check_params(p);
+    if (rc) return rc;
+    *bytes = batch_workspace(&g, 1, p, false);
+    return HPMOCD_OK;
+}
+
+int hpmocd_run_ex(const hpmocd_graph *G, const hpmocd_params *p, void *ws, size_t ws_bytes,
+                  void *stream, int flags, hpmocd_profile *prof, hpmocd_trace_fn trace,
+                  void *user, hpmocd_front **out)
+{
+    if (!G || !out || !p) return HPMOCD_ERR_ARG;
+    if (flags & HPMOCD_AUTOTUNE) return HPMOCD_ERR_ARG;  // batches only
+    hpmocd_front *f = nullptr;
+    int rc = run_batch(&G, 1, p, ws, ws_bytes, stream, flags, prof, trace, user, &f);
+    if (rc == HPMOCD_OK) *out = f;
+    return rc;
+}
+
+int hpmocd_run(const hpmocd_graph *g, const hpmocd_params *p, void *ws, size_t ws_bytes,
+               void *stream, hpmocd_front **out)
+{
+    return hpmocd_run_ex(g, p, ws, ws_bytes, stream, 0, nullptr, nullptr, nullptr, out);
+}
+
+int hpmocd_batch_workspace_size(const hpmocd_graph *const *graphs, int32_t count,
+                                const hpmocd_params *params, int flags, size_t *bytes)
+{
+    if (!bytes) return HPMOCD_ERR_ARG;
+    int rc = check_batch(graphs, count, params);
+    if (rc) return rc;
+    *bytes = batch_workspace(graphs, count, params, (flags & HPMOCD_AUTOTUNE) != 0);
+    return HPMOCD_OK;
+}
+
+int hpmocd_run_batch(const hpmocd_graph *const *graphs, int32_t count,
+                     const hpmocd_params *params, void *ws, size_t ws_bytes, void *stream,
+                     int flags, hpmocd_profile *profile, hpmocd_front **outs)
+{
+    return run_batch(graphs, count, params, ws, ws_bytes, stream, flags, profile, nullptr,
+                     nullptr, outs);
+}
+
+// ---------------------------------------------------------------------------------------
+// fitness alone (eval)
+// ---------------------------------------------------------------------------------------
+int hpmocd_eval_workspace_size(const hpmocd_graph *g, int32_t n_ind, size_t *bytes)
+{
+    if (!g || !bytes || n_ind < 1) return HPMOCD_ERR_ARG;
+    const int32_t ld = round16(n_ind);
+    const HistPlan hp = hist_plan(g->n, n_ind, g->max_deg, Tuning{}.hist_min_log2);
+    size_t b = align_up((size_t)g->n * ld * 4);  // transposed labels
+    b += hp.enabled ? align_up(hp.entries * 4) + align_up(hp.offsets * 4) : align_up((size_t)g->n * ld * 4);
+    b += 2 * align_up(8 * (size_t)n_ind) + 2 * align_up(8 * (size_t)n_ind);
+    b += meta_bytes(1);
+    *bytes = b;
+    return HPMOCD_OK;
+}
+
+int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, void *ws,
+                size_t ws_bytes, void *stream, int64_t *A, int64_t *S, double *f1, double *f2,
+                double *kernel_ms)
+{
+    if (!G || !d_labels || n_ind < 1 || !ws || !A || !S || !f1 || !f2) return HPMOCD_ERR_ARG;
+    int rc = check_device(G);
+    if (rc) return rc;
+    size_t need = 0;
+    hpmocd_eval_workspace_size(G, n_ind, &need);
+    if (ws_bytes < need) return HPMOCD_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t ld = round16(n_ind);
+    const size_t plane = (size_t)G->n * ld * 4;
+    char *p = (char *)ws;
+    int32_t *lab = (int32_t *)p;
+    p += align_up(plane);
+    Item it{};
+    it.g = dev_graph(G);
+    it.hp = hist_plan(G->n, n_ind, G->max_deg, Tuning{}.hist_min_log2);
+    if (it.hp.enabled) {
+        it.run = (uint32_t *)p;
+        p += align_up(it.hp.entries * 4);
+        it.off = (uint32_t *)p;
+        p += align_up(it.hp.offsets * 4);
+    } else {
+        it.D = (int32_t *)p;
+        it.D_bytes = plane;
+        p += align_up(plane);
+    }
+    unsigned long long *dA = (unsigned long long *)p;
+    p += align_up(8 * (size_t)n_ind);
+    unsigned long long *dS = (unsigned long long *)p;
+    p += align_up(8 * (size_t)n_ind);
+    double *df1 = (double *)p;
+    p += align_up(8 * (size_t)n_ind);
+    double *df2 = (double *)p;
+    p += align_up(8 * (size_t)n_ind);
+    it.lab = lab;
+    it.fit_pop = n_ind;
+    it.fit_ld = ld;
+    it.fit_A = dA;
+    it.fit_S = dS;
+    Tuning t;
+    it.fit_npw = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, G->n / t.fit_target_waves));
+    it.xo_nb = 1;
+    it.c.pop = n_ind;
+    Meta m;
+    std::vector<Item> items(1, it);
+    if ((rc = m.upload(items, p))) return rc;
+    HIP_TRY(m.launch(K_CLEAR, s));
+    HIP_TRY(m.one(ONE_ZERO_ACC, s));
+    HIP_TRY(launch_transpose_in(d_labels, G->n, n_ind, ld, lab, s));
+    EventSet evs;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (kernel_ms) {
+        a = evs.make();
+        b = evs.make();
+        if (!a || !b) return HPMOCD_ERR_HIP;
+        HIP_TRY(hipEventRecord(a, s));
+    }
+    HIP_TRY(launch_fitness_kinds(m, s));
+    if (kernel_ms) HIP_TRY(hipEventRecord(b, s));
+    HIP_TRY(launch_finalize(G->m2, n_ind, dA, dS, df1, df2, s));
+    std::vector<unsigned long long> hA(n_ind), hS(n_ind);
+    HIP_TRY(hipMemcpyAsync(hA.data(), dA, sizeof(unsigned long long) * n_ind, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hS.data(), dS, sizeof(unsigned long long) * n_ind, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(f1, df1, sizeof(double) * n_ind, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(f2, df2, sizeof(double) * n_ind, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int32_t i = 0; i < n_ind; ++i) {
+        A[i] = (int64_t)hA[i];
+        S[i] = (int64_t)hS[i];
+    }
+    if (kernel_ms) *kernel_ms = elapsed(a, b);
+    return HPMOCD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Batch runner internals (host side): populations, their workspace layout, item tables and
+// launch-shape tuning. Used by the run, eval and server translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "host.hpp"
+
+namespace hpm {
+
+size_t align_up(size_t x);
+int32_t round16(int32_t x);
+
+// Launch-shape knobs. Every value gives identical results; they only change how the work is
+// cut into workgroups (the autotuner picks them per batch).
+struct Tuning {
+    int32_t fit_target_waves = 16384;  // arc-scan waves wanted over the batch
+    int32_t xo_target_blocks = 2048;   // crossover/init workgroups wanted over the batch
+    int32_t mut_target_items = 96;     // mutations queued per wave group (small degrees)
+    int32_t hist_min_log2 = 20;        // binned histogram from 2^k (node, individual) pairs
+};
+
+struct RunLayout {
+    int32_t ld = 0;
+    size_t plane = 0;  // bytes of one node-major [n][ld] int32 plane
+    int32_t *pool[2] = {nullptr, nullptr};
+    int32_t *q[2] = {nullptr, nullptr};
+    int32_t *C = nullptr;
+    int32_t *D = nullptr;                     // plain histogram plane
+    HistPlan hp;
+    uint32_t *run = nullptr, *off = nullptr;  // binned histogram areas
+    DevState st{};
+    size_t bytes = 0;
+};
+
+RunLayout carve_run(void *ws, int32_t n, int32_t pop, int32_t es, int32_t max_deg,
+                    int32_t hist_min_log2, bool both_histograms);
+GaConst ga_const(const hpmocd_params *p, int32_t ld, int32_t mut_target);
+
+enum ItemWhich { ITEM_INIT = 0, ITEM_PARITY0, ITEM_PARITY1 };
+
+// One population on one graph.
+struct Pop {
+    const hpmocd_graph *G = nullptr;
+    hpmocd_params p{};
+    RunLayout L;
+    GaConst c{};
+    DevGraph dg{};
+    int32_t fit_npw = 1, xo_nb = 1;
+    int cur = 0;  // buffer parity: pool[cur] / q[cur] hold the current population
+    void setup(const hpmocd_graph *graph, const hpmocd_params &params, void *ws, const Tuning &t,
+               int64_t batch_nodes, bool both_histograms);
+    Item item(int which) const;
+};
+
+// Device tables of one set of items: the items and, per launch kind, the block offsets.
+struct Meta {
+    Item *items = nullptr;
+    int32_t *starts = nullptr;
+    int32_t count = 0;
+    int32_t totals[N_KINDS] = {};
+    size_t lds[N_KINDS] = {};
+    int32_t aux[N_KINDS] = {};
+    Span span(Kind k) const { return Span{items, starts + (size_t)k * (count + 1), count}; }
+    int upload(const std::vector<Item> &host_items, void *region);
+    hipError_t launch(Kind k, hipStream_t s) const;
+    hipError_t one(OneKernel which, hipStream_t s) const;
+};
+size_t meta_bytes(int32_t count);
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+struct EventSet {
+    std::vector<hipEvent_t> all;
+    ~EventSet();
+    hipEvent_t make();
+};
+float elapsed(hipEvent_t a, hipEvent_t b);
+
+hipError_t launch_fitness_kinds(const Meta &m, hipStream_t s);
+hipError_t launch_init_seq(const Meta &m, hipStream_t s);
+hipError_t launch_generation(const Meta &m, hipStream_t s, const EventPair *ev);
+int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, void *user,
+               bool with_labels);
+int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out);
+
+struct Batch {
+    std::vector<Pop> pops;
+    Meta meta[3];  // init, parity 0, parity 1
+    Tuning tuning;
+    int setup(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_params *params,
+              void *ws, size_t ws_bytes, const Tuning &t, bool both);
+    int generations(int32_t first, int32_t last, hipStream_t s, bool use_graph,
+                    std::vector<std::vector<EventPair>> *ev, hpmocd_trace_fn trace, void *user,
+                    bool trace_labels);
+};
+
+}  // namespace hpm
