@@ -85,6 +85,66 @@ def cpu_baseline(g, seed: int, target_s: float = 15.0):
                       f"serial C oracle, {dt:.2f} s"}
 
 
+def bench_batched(args):
+    """Batched form: many independent runs (each graph with its own pop-64 population) in one
+    batched call vs the same runs one after another; results must be identical."""
+    import numpy as np
+    import torch
+
+    import paper_2506_01752_amd as hp
+    import synth
+
+    t0 = time.perf_counter()
+    specs = synth.batch_params(args.batched, seed=0)
+    graphs = [synth.batch_graph(p) for p in specs]
+    print(f"# {len(graphs)} graphs built in {time.perf_counter() - t0:.1f} s, total n = "
+          f"{sum(g.n for g in graphs)}, total m = {sum(g.m for g in graphs)}",
+          file=sys.stderr, flush=True)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    dgs = [hp.Graph(g.row_ptr, g.col) for g in graphs]
+    params = hp.make_params(pop_size=64, generations=args.generations, crossover_p=0.9,
+                            mutation_p=0.1, parents_per_child=4, seed=0)
+    ws = torch.empty(hp.batch_workspace_size(dgs, params, hp.AUTOTUNE), dtype=torch.uint8,
+                     device="cuda")
+    # warm-up (also builds the kernels' code objects)
+    hp.run_batch(dgs[:2], params, stream=stream, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fronts_b, prof = hp.run_batch(dgs, params, stream=stream, workspace=ws, flags=hp.AUTOTUNE,
+                                  profile=True)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"# batched {t_batch:.3f} s (autotune probes {prof['tune_probe_ms']:.1f} ms)",
+          file=sys.stderr, flush=True)
+    single_ws = torch.empty(max(hp.workspace_size(d, params) for d in dgs), dtype=torch.uint8,
+                            device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fronts_s = [hp.run(d, params, stream=stream, workspace=single_ws) for d in dgs]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    identical = all(
+        np.array_equal(a.labels, b.labels) and np.array_equal(a.A, b.A)
+        and np.array_equal(a.S, b.S) and a.selected == b.selected
+        for a, b in zip(fronts_b, fronts_s))
+    out = {
+        "metric": "batched runs/s (pop 64, 100 generations per run)",
+        "value": len(dgs) / t_batch, "unit": "runs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"batch_{len(dgs)}_planted_partition",
+                   "n_total": sum(g.n for g in graphs), "m_total": sum(g.m for g in graphs),
+                   "pop_size": 64, "generations": args.generations},
+        "sequential_runs_per_s": len(dgs) / t_seq,
+        "speedup_vs_sequential": t_seq / t_batch,
+        "identical_to_sequential": identical,
+        "batched_loop_ms": prof["loop_ms"], "autotune_probe_ms": prof["tune_probe_ms"],
+        "tuning": {k: prof[k] for k in prof if k.startswith("tune_") and k != "tune_probe_ms"},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +156,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--graph-mode", action="store_true",
                     help="also time runs whose generation loop is replayed from a hipGraph")
+    ap.add_argument("--batched", type=int, default=0, metavar="COUNT",
+                    help="batched form instead: COUNT planted-partition graphs (|V| log-uniform "
+                         "in [500, 50000]), pop 64, in one batched run vs COUNT sequential runs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (calibrates "
                          "the memory-traffic counters) and exit")
@@ -114,6 +177,8 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.batched:
+        return bench_batched(args)
 
     import torch
 
