@@ -30,6 +30,62 @@ struct FastDiv {
     }
 };
 
+// Buffer pointers read from the item tables are generic to the compiler: it would emit flat
+// memory instructions (which also count against the LDS/scalar counter) and keep
+// wave-uniform loads such as CSR row offsets off the scalar unit. Every hot kernel re-types
+// the buffers it touches as global-address-space pointers first.
+#define GLB __attribute__((address_space(1)))
+template <class T> __device__ __forceinline__ GLB T *glb(T *p) { return (GLB T *)p; }
+
+// device-scope relaxed atomic addition on global memory, returning the old value
+template <class T> __device__ __forceinline__ T gatomic_add(GLB T *p, T v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// DevGraph with global-address-space pointers (degree-class bounds are read from the item
+// table directly: a private copy indexed at run time would live in scratch memory)
+struct GGraph {
+    int32_t n;
+    int64_t m2;
+    const GLB int32_t *row_ptr;
+    const GLB int32_t *col;
+    const GLB int32_t *small_nodes;
+    const GLB int32_t *large_nodes;
+    int32_t n_small, n_large, large_max_deg;
+};
+__device__ __forceinline__ GGraph gview(const DevGraph &g)
+{
+    GGraph v;
+    v.n = g.n;
+    v.m2 = g.m2;
+    v.row_ptr = glb(g.row_ptr);
+    v.col = glb(g.col);
+    v.small_nodes = glb(g.small_nodes);
+    v.large_nodes = glb(g.large_nodes);
+    v.n_small = g.n_small;
+    v.n_large = g.n_large;
+    v.large_max_deg = g.large_max_deg;
+    return v;
+}
+
+// DevState fields the variation kernels read
+struct GState {
+    const GLB int32_t *gen;
+    const GLB int32_t *pos_id;
+    const GLB int32_t *par_id;
+    const GLB int32_t *gate;
+};
+__device__ __forceinline__ GState gview(const DevState &s)
+{
+    GState v;
+    v.gen = glb(s.gen);
+    v.pos_id = glb(s.pos_id);
+    v.par_id = glb(s.par_id);
+    v.gate = glb(s.gate);
+    return v;
+}
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 
 __device__ __forceinline__ int wave_max(int v)
@@ -125,9 +181,9 @@ __global__ __launch_bounds__(256) void k_init(Span sp)
 {
     int lb, nblk;
     const Item &it = sp.items[item_of(sp, lb, nblk)];
-    const DevGraph g = it.g;
+    const GGraph g = gview(it.g);
     const GaConst c = it.c;
-    int32_t *__restrict__ Q = const_cast<int32_t *>(it.q_cur);
+    GLB int32_t *__restrict__ Q = glb(const_cast<int32_t *>(it.q_cur));
     const FastDiv divpop((uint32_t)c.pop);
     const int64_t v0 = (int64_t)lb * NODE_BLOCK;
     const int nv = (int)min((int64_t)NODE_BLOCK, (int64_t)g.n - v0);
@@ -173,16 +229,16 @@ __global__ __launch_bounds__(256) void k_fitness(Span sp)
 {
     int lb, nblk;
     const Item &it = sp.items[item_of(sp, lb, nblk)];
-    const DevGraph g = it.g;
-    const int32_t *__restrict__ lab = it.lab;
+    const GGraph g = gview(it.g);
+    const GLB int32_t *__restrict__ lab = glb(it.lab);
     const int32_t ld = it.fit_ld, pop = it.fit_pop, npw = it.fit_npw;
     const int nchunks = (pop + 127) / 128;
-    int32_t *__restrict__ D = it.D;
-    unsigned long long *__restrict__ A = it.fit_A;
-    unsigned long long *__restrict__ S = it.fit_S;
+    GLB int32_t *__restrict__ D = glb(it.D);
+    GLB unsigned long long *__restrict__ A = glb(it.fit_A);
+    GLB unsigned long long *__restrict__ S = glb(it.fit_S);
     const int atomics_phase = it.hp.enabled ? 0 : 1;
     const int lane = lane_id();
-    const int wave = lb * 4 + (int)(threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
     const int chunk = wave % nchunks;
     const int32_t v0 = (int32_t)min((int64_t)(wave / nchunks) * npw, (int64_t)g.n);
     if (v0 >= g.n) return;
@@ -190,7 +246,7 @@ __global__ __launch_bounds__(256) void k_fitness(Span sp)
     const int c0 = chunk * 128 + 2 * lane;
     const bool act1 = c0 + 1 < pop;
     if (c0 >= pop) return;
-    const int32_t *__restrict__ lc = lab + c0;
+    const GLB int32_t *__restrict__ lc = lab + c0;
 
     // phase 1: intra-community arcs
     int cnt0 = 0, cnt1 = 0;
@@ -239,8 +295,8 @@ __global__ __launch_bounds__(256) void k_fitness(Span sp)
         for (int k = 0; k < FIT_NODES; ++k) {
             o0[k] = o1[k] = 0;
             if (d[k] > 0) {
-                o0[k] = atomicAdd(D + (size_t)own[k].x * ld + c0, d[k]);
-                if (act1) o1[k] = atomicAdd(D + (size_t)own[k].y * ld + c0 + 1, d[k]);
+                o0[k] = gatomic_add(D + (size_t)own[k].x * ld + c0, d[k]);
+                if (act1) o1[k] = gatomic_add(D + (size_t)own[k].y * ld + c0 + 1, d[k]);
             }
         }
 #pragma unroll
@@ -249,11 +305,11 @@ __global__ __launch_bounds__(256) void k_fitness(Span sp)
             s1 += sq_step(o1[k], d[k]);
         }
     }
-    atomicAdd(A + c0, (unsigned long long)cnt0);
-    if (act1) atomicAdd(A + c0 + 1, (unsigned long long)cnt1);
+    gatomic_add(A + c0, (unsigned long long)cnt0);
+    if (act1) gatomic_add(A + c0 + 1, (unsigned long long)cnt1);
     if (atomics_phase) {
-        atomicAdd(S + c0, s0);
-        if (act1) atomicAdd(S + c0 + 1, s1);
+        gatomic_add(S + c0, s0);
+        if (act1) gatomic_add(S + c0 + 1, s1);
     }
 }
 
@@ -322,12 +378,12 @@ __global__ __launch_bounds__(256) void k_bin(Span sp)
 {
     int lb, nblk;
     const Item &it = sp.items[item_of(sp, lb, nblk)];
-    const DevGraph g = it.g;
-    const int32_t *__restrict__ lab = it.lab;
+    const GGraph g = gview(it.g);
+    const GLB int32_t *__restrict__ lab = glb(it.lab);
     const int32_t ld = it.fit_ld, pop = it.fit_pop;
     const HistPlan p = it.hp;
-    uint32_t *__restrict__ run = it.run;
-    uint32_t *__restrict__ off = it.off;
+    GLB uint32_t *__restrict__ run = glb(it.run);
+    GLB uint32_t *__restrict__ off = glb(it.off);
     extern __shared__ uint32_t bl[];
     const int counters = p.tiles * HB_CG;
     uint32_t *cnt = bl;                             // [counters + 1]
@@ -374,7 +430,7 @@ __global__ __launch_bounds__(256) void k_bin(Span sp)
     }
     if (threadIdx.x == 0) cnt[counters] = total;
     __syncthreads();
-    uint32_t *o = off + ((size_t)chunk * p.ngroups + grp) * (size_t)(counters + 1);
+    GLB uint32_t *o = off + ((size_t)chunk * p.ngroups + grp) * (size_t)(counters + 1);
     for (int i = threadIdx.x; i <= counters; i += blockDim.x) o[i] = cnt[i];
     __syncthreads();
     for (int base = 0; base < items; base += (int)blockDim.x * BIN_UNROLL) {
@@ -398,7 +454,7 @@ __global__ __launch_bounds__(256) void k_bin(Span sp)
         }
     }
     __syncthreads();
-    uint32_t *dst = run + ((size_t)grp * p.nchunks + chunk) * ((size_t)p.nb * HB_CG);
+    GLB uint32_t *dst = run + ((size_t)grp * p.nchunks + chunk) * ((size_t)p.nb * HB_CG);
     for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) dst[i] = stage[i];
 }
 
@@ -409,9 +465,9 @@ __global__ __launch_bounds__(256) void k_hist(Span sp)
     int lb, nblk;
     const Item &it = sp.items[item_of(sp, lb, nblk)];
     const HistPlan p = it.hp;
-    const uint32_t *__restrict__ run = it.run;
-    const uint32_t *__restrict__ off = it.off;
-    unsigned long long *__restrict__ S = it.fit_S;
+    const GLB uint32_t *__restrict__ run = glb(it.run);
+    const GLB uint32_t *__restrict__ off = glb(it.off);
+    GLB unsigned long long *__restrict__ S = glb(it.fit_S);
     extern __shared__ uint32_t hist[];  // [2^rbits], the whole 64 KB at most
     const int t = lb % p.tiles, j = lb / p.tiles;
     const int grp = j / HB_CG, jl = j % HB_CG;
@@ -431,7 +487,7 @@ __global__ __launch_bounds__(256) void k_hist(Span sp)
             const int w = w0 + k * (int)blockDim.x + (int)threadIdx.x;
             b0[k] = b1[k] = 0;
             if (w < p.nchunks) {
-                const uint32_t *o = off + ((size_t)w * p.ngroups + grp) * (size_t)(counters + 1) + bucket;
+                const GLB uint32_t *o = off + ((size_t)w * p.ngroups + grp) * (size_t)(counters + 1) + bucket;
                 b0[k] = o[0];
                 b1[k] = o[1];
             }
@@ -439,7 +495,7 @@ __global__ __launch_bounds__(256) void k_hist(Span sp)
 #pragma unroll
         for (int k = 0; k < WPT; ++k) {
             const int w = w0 + k * (int)blockDim.x + (int)threadIdx.x;
-            const uint32_t *src = run + ((size_t)grp * p.nchunks + (size_t)(w < p.nchunks ? w : 0)) * span;
+            const GLB uint32_t *src = run + ((size_t)grp * p.nchunks + (size_t)(w < p.nchunks ? w : 0)) * span;
             for (uint32_t e = b0[k]; e < b1[k]; e += HIST_UNROLL) {
                 uint32_t x[HIST_UNROLL];
 #pragma unroll
@@ -458,7 +514,7 @@ __global__ __launch_bounds__(256) void k_hist(Span sp)
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o);
-    if (lane_id() == 0 && sq != 0) atomicAdd(S + j, sq);  // one atomic per wave
+    if (lane_id() == 0 && sq != 0) gatomic_add(S + j, sq);  // one atomic per wave
 }
 
 // clears the plain histogram plane of every item (write-only stream)
@@ -825,12 +881,12 @@ __global__ __launch_bounds__(256) void k_crossover(Span sp)
     const Item &it = sp.items[item_of(sp, lb, nblk)];
     const int32_t n = it.g.n, nblock = it.xo_nb;
     const GaConst c = it.c;
-    const DevState st = it.st;
-    const int32_t *__restrict__ pool_cur = it.pool_cur;
-    const int32_t *__restrict__ q_cur = it.q_cur;
-    int32_t *__restrict__ pool_new = it.pool_new;
-    int32_t *__restrict__ C = it.C;
-    int32_t *__restrict__ q_next = it.q_next;
+    const GState st = gview(it.st);
+    const GLB int32_t *__restrict__ pool_cur = glb(it.pool_cur);
+    const GLB int32_t *__restrict__ q_cur = glb(it.q_cur);
+    GLB int32_t *__restrict__ pool_new = glb(it.pool_new);
+    GLB int32_t *__restrict__ C = glb(it.C);
+    GLB int32_t *__restrict__ q_next = glb(it.q_next);
     const FastDiv divpop((uint32_t)c.pop);
     extern __shared__ int xs[];  // [pop] pos_id, [pop] gate, [pop * ES] par_id
     const int pop = c.pop, ld = c.ld;
@@ -863,8 +919,8 @@ __global__ __launch_bounds__(256) void k_crossover(Span sp)
             jj[t] = (int)(fq - q * (uint32_t)pop);
             vv[t] = (uint32_t)(v0 + q);
             row[t] = (size_t)vv[t] * ld;
-            const int32_t *prow = pool_cur + row[t];
-            const int32_t *qrow = q_cur + row[t] - pop;  // indexed by id >= pop
+            const GLB int32_t *prow = pool_cur + row[t];
+            const GLB int32_t *qrow = q_cur + row[t] - pop;  // indexed by id >= pop
             const int id = s_pos[jj[t]];
             commit[t] = id < pop ? prow[id] : qrow[id];
             gk[t] = s_gate[jj[t]];
@@ -913,8 +969,8 @@ __device__ __forceinline__ void bitonic_regs(int (&a)[K])
 
 // Plurality of d <= K labels held by this lane (one mutation per lane).
 template <int K>
-__device__ __forceinline__ int lane_plurality(const int32_t *__restrict__ C, int ld, int j,
-                                              const int32_t *__restrict__ nbr, int d, uint32_t r)
+__device__ __forceinline__ int lane_plurality(const GLB int32_t *__restrict__ C, int ld, int j,
+                                              const GLB int32_t *__restrict__ nbr, int d, uint32_t r)
 {
     int a[K];
 #pragma unroll
@@ -965,17 +1021,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_mutate_lanes(Span sp, int cls)
 {
     int lb, nblk;
     const Item &it = sp.items[item_of(sp, lb, nblk)];
-    const DevGraph g = it.g;
+    const GGraph g = gview(it.g);
     const GaConst c = it.c;
-    const DevState st = it.st;
-    const int32_t *__restrict__ C = it.C;
-    int32_t *__restrict__ q_next = it.q_next;
-    const int32_t cstart = cls == 0 ? 0 : g.class_end[cls - 1];
-    const int32_t *__restrict__ list = g.small_nodes + cstart;
-    const int32_t count_nodes = g.class_end[cls] - cstart;
+    const GState st = gview(it.st);
+    const GLB int32_t *__restrict__ C = glb(it.C);
+    GLB int32_t *__restrict__ q_next = glb(it.q_next);
+    const int32_t cstart = cls == 0 ? 0 : it.g.class_end[cls - 1];
+    const GLB int32_t *__restrict__ list = g.small_nodes + cstart;
+    const int32_t count_nodes = it.g.class_end[cls] - cstart;
     const FastDiv divpop((uint32_t)c.pop);
     __shared__ uint2 items[WAVES][MUT_LIST_CAP];
-    const int wv = threadIdx.x >> 6, lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = lane_id();
     const uint32_t gen = (uint32_t)*st.gen;
     const int pop = c.pop, G = c.mut_group;
     const int ngroups = (count_nodes + G - 1) / G;
@@ -1010,7 +1066,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mutate_lanes(Span sp, int cls)
             const int j = (int)(it.x & 0xFFFFu);
             const int32_t rs = g.row_ptr[node];
             const int d = has ? g.row_ptr[node + 1] - rs : 0;
-            const int32_t *nbr = g.col + rs;
+            const GLB int32_t *nbr = g.col + rs;
             int res;
             if constexpr (KMAX == 16) {
                 const int dmax = wave_max(d);
@@ -1068,8 +1124,8 @@ __device__ __forceinline__ void wave_bitonic(int (&a)[E])
 }
 
 template <int E>
-__device__ __forceinline__ int wave_plurality(const int32_t *__restrict__ C, int ld, int j,
-                                              const int32_t *__restrict__ nbr, int d, uint32_t r)
+__device__ __forceinline__ int wave_plurality(const GLB int32_t *__restrict__ C, int ld, int j,
+                                              const GLB int32_t *__restrict__ nbr, int d, uint32_t r)
 {
     const int lane = lane_id();
     int a[E];
@@ -1139,23 +1195,23 @@ __global__ __launch_bounds__(256) void k_mutate_wave(Span sp, int cls)
 {
     int lb, nblk;
     const Item &it = sp.items[item_of(sp, lb, nblk)];
-    const DevGraph g = it.g;
+    const GGraph g = gview(it.g);
     const GaConst c = it.c;
-    const DevState st = it.st;
-    const int32_t *__restrict__ C = it.C;
-    int32_t *__restrict__ q_next = it.q_next;
-    const int32_t cstart = cls == 0 ? 0 : g.class_end[cls - 1];
-    const int32_t *__restrict__ list = g.small_nodes + cstart;
-    const int32_t count_nodes = g.class_end[cls] - cstart;
+    const GState st = gview(it.st);
+    const GLB int32_t *__restrict__ C = glb(it.C);
+    GLB int32_t *__restrict__ q_next = glb(it.q_next);
+    const int32_t cstart = cls == 0 ? 0 : it.g.class_end[cls - 1];
+    const GLB int32_t *__restrict__ list = g.small_nodes + cstart;
+    const int32_t count_nodes = it.g.class_end[cls] - cstart;
     __shared__ uint2 items[MUT_WAVES][HPMOCD_MAX_POP_DEV];
-    const int wv = threadIdx.x >> 6, lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = lane_id();
     const uint32_t gen = (uint32_t)*st.gen;
     const int pop = c.pop, ld = c.ld;
     for (int t = lb * MUT_WAVES + wv; t < count_nodes; t += nblk * MUT_WAVES) {
         const int32_t node = list[t];
         const int32_t rs = g.row_ptr[node];
         const int d = g.row_ptr[node + 1] - rs;
-        const int32_t *nbr = g.col + rs;
+        const GLB int32_t *nbr = g.col + rs;
         int count = 0;
         for (int j0 = 0; j0 < pop; j0 += 64) {
             const int j = j0 + lane;
@@ -1228,8 +1284,8 @@ __device__ int sorted_plurality(const int *buf, int d, uint32_t r, int *res_slot
 }
 
 // exact plurality by walking the distinct labels in ascending order (any degree, slow)
-__device__ int scan_plurality(const int32_t *__restrict__ C, int ld, int j,
-                              const int32_t *__restrict__ nbr, int d, uint32_t r)
+__device__ int scan_plurality(const GLB int32_t *__restrict__ C, int ld, int j,
+                              const GLB int32_t *__restrict__ nbr, int d, uint32_t r)
 {
     const int lane = lane_id();
     int best = 0, nt = 0, prev = -1;
@@ -1279,16 +1335,16 @@ __global__ __launch_bounds__(128) void k_mutate_large(Span sp, int pmax)
 {
     int lb, nblk;
     const Item &it = sp.items[item_of(sp, lb, nblk)];
-    const DevGraph g = it.g;
+    const GGraph g = gview(it.g);
     const GaConst c = it.c;
-    const DevState st = it.st;
-    const int32_t *__restrict__ C = it.C;
-    int32_t *__restrict__ q_next = it.q_next;
+    const GState st = gview(it.st);
+    const GLB int32_t *__restrict__ C = glb(it.C);
+    GLB int32_t *__restrict__ q_next = glb(it.q_next);
     extern __shared__ int lds[];
     uint2 *items = (uint2 *)lds;                    // [pop]
     int *res = lds + 2 * HPMOCD_MAX_POP_DEV;        // [MUT_WAVES]
     int *cnt_sh = res + MUT_WAVES;                  // [1]
-    const int wv = threadIdx.x >> 6, lane = lane_id();
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = lane_id();
     const int nwaves = (int)(blockDim.x >> 6);
     int *buf = cnt_sh + 4 + wv * pmax;              // [pmax] per wave
     const uint32_t gen = (uint32_t)*st.gen;
@@ -1297,7 +1353,7 @@ __global__ __launch_bounds__(128) void k_mutate_large(Span sp, int pmax)
         const int32_t node = g.large_nodes[t];
         const int32_t rs = g.row_ptr[node];
         const int d = g.row_ptr[node + 1] - rs;
-        const int32_t *nbr = g.col + rs;
+        const GLB int32_t *nbr = g.col + rs;
         if (threadIdx.x == 0) *cnt_sh = 0;
         __syncthreads();
         for (int j = threadIdx.x; j < pop; j += blockDim.x) {
@@ -1450,8 +1506,8 @@ int32_t kind_blocks(Kind k, const Item &it)
     }
     const int cls = (int)k - (int)K_MUT0;
     if (cls < 0 || cls >= N_DEG_CLASSES || it.c.thr_m == 0) return 0;
-    const int32_t start = cls == 0 ? 0 : g.class_end[cls - 1];
-    const int32_t cnt = g.class_end[cls] - start;
+    const int32_t start = cls == 0 ? 0 : it.g.class_end[cls - 1];
+    const int32_t cnt = it.g.class_end[cls] - start;
     if (cnt <= 0) return 0;
     if (DEG_CLASS_MAX[cls] <= 32) {
         const int32_t b = ceil_div(ceil_div(cnt, it.c.mut_group), MUT_WAVES);
