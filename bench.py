@@ -145,6 +145,133 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def _request_graph(p):
+    import synth
+    g = synth.batch_graph(p)
+    return g.row_ptr, g.col
+
+
+def bench_served(args):
+    """Served form: a Poisson stream of community-detection requests against the
+    continuous-batching server, at about 0.5x and 0.9x of its measured capacity, and the
+    same streams against the plain FIFO server (one resident request at a time). Every
+    request's front must be identical in both."""
+    import multiprocessing as mp
+
+    import numpy as np
+
+    import synth
+
+    count = args.served
+    specs = synth.request_stream(count, rate=1.0, seed=0)   # arrival times at rate 1
+    t0 = time.perf_counter()
+    # graphs are built in worker processes before this process touches the device
+    with mp.get_context("fork").Pool(min(16, os.cpu_count() or 1)) as pool:
+        graphs = pool.map(_request_graph, specs, chunksize=4)
+    n_tot = sum(len(rp) - 1 for rp, _ in graphs)
+    m_tot = sum(len(c) // 2 for _, c in graphs)
+    print(f"# {count} request graphs built in {time.perf_counter() - t0:.1f} s: total n = "
+          f"{n_tot}, total m = {m_tot}", file=sys.stderr, flush=True)
+
+    import torch
+
+    import paper_2506_01752_amd as hp
+    torch.cuda.set_device(0)
+    params = hp.make_params(pop_size=100, generations=args.generations, crossover_p=0.9,
+                            mutation_p=0.1, parents_per_child=4, seed=0)
+    budget = int(args.hbm_budget_gb * (1 << 30))
+    unit = np.array([s["arrival"] for s in specs])
+
+    def serve(fifo, rate):
+        """rate None: every request at t = 0 (capacity). Returns (fronts, per-request
+        latency s, makespan s, stats)."""
+        srv = hp.Server(hbm_budget=budget, max_active=args.max_active, fifo=fifo)
+        t_create = time.monotonic()
+        arrivals = np.zeros(count) if rate is None else unit / rate
+        tickets = [None] * count
+        start = time.monotonic() + 0.05
+        nthreads = 4
+
+        def submitter(k):
+            for i in range(k, count, nthreads):
+                delay = start + arrivals[i] - time.monotonic()
+                if delay > 0:
+                    time.sleep(delay)
+                rp, col = graphs[i]
+                tickets[i] = srv.submit(rp, col, params)[0]
+
+        import threading
+        th = [threading.Thread(target=submitter, args=(k,)) for k in range(nthreads)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        fronts, lat, done = [], np.zeros(count), np.zeros(count)
+        base = start - t_create  # arrival i at server-clock time base + arrivals[i]
+        for i in range(count):
+            f, info = srv.wait(tickets[i])
+            fronts.append(f)
+            done[i] = info["done_s"]
+            lat[i] = info["done_s"] - (base + arrivals[i])
+        st = srv.stats()
+        srv.close()
+        return fronts, lat, float(done.max() - base), st
+
+    def summary(lat, makespan, st):
+        return {"runs_per_s": count / makespan, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                "p99_ms": float(np.percentile(lat, 99) * 1e3), "makespan_s": makespan,
+                "peak_active": st["peak_active"], "peak_gb": st["peak_bytes"] / 2**30,
+                "steps": st["steps"]}
+
+    # warm-up: code objects, first allocations
+    srv = hp.Server(hbm_budget=1 << 30, max_active=4)
+    rp, col = graphs[0]
+    srv.wait(srv.submit(rp, col, hp.make_params(pop_size=100, generations=2))[0])
+    srv.close()
+
+    out = {}
+    ref_fronts, lat, mk, st = serve(False, None)
+    cap = count / mk
+    out["capacity"] = summary(lat, mk, st)
+    print(f"# capacity (all at t=0): {cap:.2f} runs/s", file=sys.stderr, flush=True)
+    _, lat, mk, st = serve(True, None)
+    out["fifo_capacity"] = summary(lat, mk, st)
+    print(f"# FIFO capacity: {count / mk:.2f} runs/s", file=sys.stderr, flush=True)
+    identical = True
+    for frac in (0.5, 0.9):
+        rate = frac * cap
+        for fifo in (False, True):
+            fr, lat, mk, st = serve(fifo, rate)
+            key = f"{'fifo' if fifo else 'served'}_{frac}x"
+            out[key] = dict(summary(lat, mk, st), arrival_rate=rate)
+            identical = identical and all(
+                np.array_equal(a.labels, b.labels) and np.array_equal(a.A, b.A)
+                and np.array_equal(a.S, b.S) and a.selected == b.selected
+                for a, b in zip(fr, ref_fronts))
+            print(f"# {key}: {out[key]}", file=sys.stderr, flush=True)
+    # a few requests against the plain single-run entry point
+    stream = torch.cuda.Stream()
+    for i in range(0, count, max(1, count // 4)):
+        rp, col = graphs[i]
+        f = hp.run(hp.Graph(rp, col), params, stream=stream)
+        identical = identical and np.array_equal(f.labels, ref_fronts[i].labels) and \
+            np.array_equal(f.A, ref_fronts[i].A) and np.array_equal(f.S, ref_fronts[i].S)
+    s9 = out["served_0.9x"]
+    line = {
+        "metric": "served runs/s + p50/p99 latency (pop 100, 100 generations per request)",
+        "value": s9["runs_per_s"], "unit": "runs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": s9["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"served_{count}_poisson_planted_partition", "n_total": n_tot,
+                   "m_total": m_tot, "pop_size": 100, "generations": args.generations,
+                   "max_active": args.max_active, "hbm_budget_gb": args.hbm_budget_gb},
+        "p50_ms": s9["p50_ms"], "p99_ms": s9["p99_ms"],
+        "identical_to_alone": bool(identical),
+        "detail": out,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +286,12 @@ def main():
     ap.add_argument("--batched", type=int, default=0, metavar="COUNT",
                     help="batched form instead: COUNT planted-partition graphs (|V| log-uniform "
                          "in [500, 50000]), pop 64, in one batched run vs COUNT sequential runs")
+    ap.add_argument("--served", type=int, default=0, metavar="COUNT",
+                    help="served form instead: COUNT requests (|V| log-uniform in [1000, 200000], "
+                         "pop 100, 100 generations) arriving as a Poisson stream, continuous "
+                         "batching vs plain FIFO")
+    ap.add_argument("--max-active", type=int, default=64)
+    ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (calibrates "
                          "the memory-traffic counters) and exit")
@@ -179,6 +312,8 @@ def main():
         sys.exit(2)
     if args.batched:
         return bench_batched(args)
+    if args.served:
+        return bench_served(args)
 
     import torch
 

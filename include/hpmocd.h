@@ -37,6 +37,8 @@ extern "C" {
 #define HPMOCD_ERR_HIP -9        /* a HIP runtime call failed */
 #define HPMOCD_ERR_BUDGET -10    /* request does not fit the device-memory budget */
 #define HPMOCD_ERR_NOMEM -11     /* host allocation failed */
+#define HPMOCD_ERR_CANCELLED -12 /* server request cancelled (or the server shut down first) */
+#define HPMOCD_ERR_TIMEOUT -13   /* server wait timed out; the request is still pending */
 
 /* Largest population: the selection kernels rank 2 * pop_size points in one workgroup. */
 #define HPMOCD_MAX_POP 512
@@ -163,6 +165,78 @@ int hpmocd_eval_workspace_size(const hpmocd_graph *g, int32_t n_ind, size_t *byt
 int hpmocd_eval(const hpmocd_graph *g, const int32_t *d_labels, int32_t n_ind,
                 void *d_workspace, size_t ws_bytes, void *stream, int64_t *A, int64_t *S,
                 double *f1, double *f2, double *kernel_ms);
+
+/* Served form: a community-detection service over one device. Requests (a CSR graph plus
+ * Alg. 1 parameters) are submitted from any host thread and return at once with a ticket;
+ * a scheduler thread owned by the server admits them in arrival order while two limits
+ * hold: at most max_active resident requests, and their device bytes (graph + populations +
+ * histogram + state, reported by submit) within hbm_budget, all carved from one device arena
+ * the caller provides. Continuous batching: every scheduler step initialises the requests
+ * just admitted and advances every resident request by one generation in shared launches
+ * (requests at different generations, on different graphs, in the same kernels); a request
+ * that has run its T generations is ranked (Alg. 1 phase 4), its front copied to the host
+ * and its memory released, so requests that arrived meanwhile take its place at the next
+ * step. Populations stay on the device for the whole run. A request's front equals its
+ * hpmocd_run front bit for bit, whatever else shares the device.
+ *
+ * The arena must hold hpmocd_server_arena_overhead(max_active) bytes of tables plus the
+ * budget; it and the stream belong to the caller and must outlive the server. All requests
+ * of a server share parents_per_child (one crossover kernel shape per step). */
+typedef struct hpmocd_server hpmocd_server;
+
+#define HPMOCD_SERVER_FIFO 1          /* baseline: admit only when no request is resident */
+#define HPMOCD_SERVER_MAX_ACTIVE 4096
+
+typedef struct {
+    size_t hbm_budget;          /* device bytes resident requests may hold together */
+    int32_t max_active;         /* 1 .. HPMOCD_SERVER_MAX_ACTIVE */
+    int32_t parents_per_child;  /* E_S of every request */
+    int32_t flags;              /* HPMOCD_SERVER_FIFO or 0 */
+} hpmocd_server_config;
+
+/* Life of one request, seconds on the server's monotonic clock (0 = server creation). */
+typedef struct {
+    double submit_s, admit_s, done_s;  /* done = front on the host */
+    int64_t device_bytes;              /* bytes it held while resident */
+    int32_t steps;                     /* scheduler steps it was resident for */
+    int32_t max_mix;                   /* most requests resident together during its run */
+} hpmocd_request_info;
+
+typedef struct {
+    int64_t steps, admitted, completed, cancelled;
+    int32_t peak_active;
+    int64_t peak_bytes;
+    double busy_s;                     /* scheduler time spent in steps (host clock) */
+} hpmocd_server_stats;
+
+#define HPMOCD_REQ_QUEUED 0
+#define HPMOCD_REQ_RUNNING 1
+#define HPMOCD_REQ_DONE 2
+
+size_t hpmocd_server_arena_overhead(int32_t max_active);
+/* Starts the scheduler thread on the calling thread's current device. d_arena: device memory
+ * of arena_bytes >= overhead + hbm_budget. */
+int hpmocd_server_create(const hpmocd_server_config *cfg, void *d_arena, size_t arena_bytes,
+                         void *stream, hpmocd_server **out);
+/* Validates and copies the graph (as hpmocd_graph_create) and queues the request.
+ * HPMOCD_ERR_BUDGET if it could never fit the budget. *ticket identifies it; *device_bytes
+ * (may be NULL) receives the bytes it will hold. */
+int hpmocd_server_submit(hpmocd_server *s, int32_t n, const int32_t *row_ptr, const int32_t *col,
+                         const hpmocd_params *p, int64_t *ticket, size_t *device_bytes);
+/* *state = HPMOCD_REQ_QUEUED / RUNNING / DONE. */
+int hpmocd_server_poll(hpmocd_server *s, int64_t ticket, int32_t *state);
+/* Blocks until the request is done or timeout_s passes (< 0: no limit). On completion
+ * returns the request's status and releases the ticket; on HPMOCD_OK *out receives the front
+ * (free with hpmocd_front_free) and *info (may be NULL) its timings. */
+int hpmocd_server_wait(hpmocd_server *s, int64_t ticket, double timeout_s, hpmocd_front **out,
+                       hpmocd_request_info *info);
+/* A queued request is dropped at once, a resident one at the next step; its wait returns
+ * HPMOCD_ERR_CANCELLED. */
+int hpmocd_server_cancel(hpmocd_server *s, int64_t ticket);
+int hpmocd_server_stats_get(hpmocd_server *s, hpmocd_server_stats *out);
+/* Stops the scheduler after its current step; requests not done are cancelled and their
+ * tickets released. No other call on s may be in progress or follow. */
+void hpmocd_server_destroy(hpmocd_server *s);
 
 const char *hpmocd_strerror(int status);
 

@@ -20,14 +20,20 @@ OK = 0
 ERR = {
     -1: "ERR_ARG", -2: "ERR_CSR_ASYM", -3: "ERR_SELF_LOOP", -4: "ERR_DUP_EDGE",
     -5: "ERR_RANGE", -6: "ERR_EMPTY", -7: "ERR_TOO_LARGE", -8: "ERR_WORKSPACE",
-    -9: "ERR_HIP", -10: "ERR_BUDGET", -11: "ERR_NOMEM",
+    -9: "ERR_HIP", -10: "ERR_BUDGET", -11: "ERR_NOMEM", -12: "ERR_CANCELLED",
+    -13: "ERR_TIMEOUT",
 }
+ERR_BUDGET = -10
+ERR_CANCELLED = -12
+ERR_TIMEOUT = -13
 MAX_POP = 512
 MAX_PARENTS = 8
 NO_GRAPH = 1
 TIME_KERNELS = 2
 TRACE_NO_LABELS = 4
 AUTOTUNE = 8
+SERVER_FIFO = 1
+REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 
 # every entry point that include/hpmocd.h declares
 EXPORTS = [
@@ -35,6 +41,9 @@ EXPORTS = [
     "hpmocd_workspace_size", "hpmocd_run", "hpmocd_run_ex", "hpmocd_front_free",
     "hpmocd_eval_workspace_size", "hpmocd_eval", "hpmocd_strerror",
     "hpmocd_batch_workspace_size", "hpmocd_run_batch",
+    "hpmocd_server_arena_overhead", "hpmocd_server_create", "hpmocd_server_submit",
+    "hpmocd_server_poll", "hpmocd_server_wait", "hpmocd_server_cancel",
+    "hpmocd_server_stats_get", "hpmocd_server_destroy",
 ]
 
 
@@ -78,6 +87,28 @@ class Profile(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32),
+                ("parents_per_child", C.c_int32), ("flags", C.c_int32)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double),
+                ("device_bytes", C.c_int64), ("steps", C.c_int32), ("max_mix", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("cancelled", C.c_int64), ("peak_active", C.c_int32),
+                ("peak_bytes", C.c_int64), ("busy_s", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _TRACE = C.CFUNCTYPE(None, C.POINTER(_View), C.c_void_p)
 _lib = None
 
@@ -111,11 +142,25 @@ def lib():
         L.hpmocd_run_batch.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(Params), vp,
                                        C.c_size_t, vp, C.c_int, C.POINTER(Profile),
                                        C.POINTER(C.POINTER(_Front))]
+        L.hpmocd_server_arena_overhead.argtypes = [C.c_int32]
+        L.hpmocd_server_create.argtypes = [C.POINTER(ServerConfig), vp, C.c_size_t, vp,
+                                           C.POINTER(vp)]
+        L.hpmocd_server_submit.argtypes = [vp, C.c_int32, i32p, i32p, C.POINTER(Params), i64p,
+                                           C.POINTER(C.c_size_t)]
+        L.hpmocd_server_poll.argtypes = [vp, C.c_int64, i32p]
+        L.hpmocd_server_wait.argtypes = [vp, C.c_int64, C.c_double,
+                                         C.POINTER(C.POINTER(_Front)), C.POINTER(RequestInfo)]
+        L.hpmocd_server_cancel.argtypes = [vp, C.c_int64]
+        L.hpmocd_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
+        L.hpmocd_server_destroy.argtypes = [vp]
+        L.hpmocd_server_destroy.restype = None
         L.hpmocd_strerror.argtypes = [C.c_int]
         L.hpmocd_strerror.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("hpmocd_graph_destroy", "hpmocd_front_free", "hpmocd_strerror"):
+            if name not in ("hpmocd_graph_destroy", "hpmocd_front_free", "hpmocd_strerror",
+                            "hpmocd_server_destroy", "hpmocd_server_arena_overhead"):
                 getattr(L, name).restype = C.c_int
+        L.hpmocd_server_arena_overhead.restype = C.c_size_t
         _lib = L
     return _lib
 
@@ -328,3 +373,73 @@ def evaluate(graph: Graph, labels, *, stream=None, timing=False):
                              f2.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ms)),
            "hpmocd_eval")
     return (A, S, f1, f2, ms.value) if timing else (A, S, f1, f2)
+
+
+class Server:
+    """hpmocd_server_*: continuous-batching service on the current device. The arena (device
+    memory: table overhead + hbm_budget bytes) and the stream come from torch and are kept
+    alive by this object. submit() returns a ticket at once; wait() blocks until the front
+    is on the host (the GIL is released meanwhile)."""
+
+    def __init__(self, hbm_budget: int, max_active: int = 256, parents_per_child: int = 4,
+                 fifo: bool = False, stream=None):
+        import torch
+        self._h = C.c_void_p()
+        over = lib().hpmocd_server_arena_overhead(max_active)
+        self.arena = torch.empty(over + hbm_budget, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        cfg = ServerConfig(hbm_budget, max_active, parents_per_child, SERVER_FIFO if fifo else 0)
+        _check(lib().hpmocd_server_create(C.byref(cfg), C.c_void_p(self.arena.data_ptr()),
+                                          self.arena.numel(), C.c_void_p(self.stream.cuda_stream),
+                                          C.byref(self._h)), "hpmocd_server_create")
+
+    def submit(self, row_ptr, col, params: Params | None = None, **kw):
+        """Queues one run; returns (ticket, device bytes it will hold)."""
+        if params is None:
+            params = make_params(**kw)
+        rp, cl = _i32(row_ptr), _i32(col)
+        t, b = C.c_int64(), C.c_size_t()
+        _check(lib().hpmocd_server_submit(self._h, len(rp) - 1,
+                                          rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                                          cl.ctypes.data_as(C.POINTER(C.c_int32)),
+                                          C.byref(params), C.byref(t), C.byref(b)),
+               "hpmocd_server_submit")
+        return t.value, b.value
+
+    def poll(self, ticket: int) -> int:
+        st = C.c_int32()
+        _check(lib().hpmocd_server_poll(self._h, ticket, C.byref(st)), "hpmocd_server_poll")
+        return st.value
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        """(Front, info dict); raises HpmocdError (ERR_TIMEOUT, ERR_CANCELLED, ...)."""
+        out = C.POINTER(_Front)()
+        info = RequestInfo()
+        _check(lib().hpmocd_server_wait(self._h, ticket, float(timeout), C.byref(out),
+                                        C.byref(info)), "hpmocd_server_wait")
+        return _front_from(out), info.as_dict()
+
+    def cancel(self, ticket: int):
+        _check(lib().hpmocd_server_cancel(self._h, ticket), "hpmocd_server_cancel")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(lib().hpmocd_server_stats_get(self._h, C.byref(st)), "hpmocd_server_stats_get")
+        return st.as_dict()
+
+    def close(self):
+        if self._h:
+            lib().hpmocd_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

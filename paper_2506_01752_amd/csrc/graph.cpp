@@ -12,6 +12,127 @@ namespace hpm {
 
 constexpr int64_t MAX_ARCS_EXACT = 94906265;  // largest 2m with (2m)^2 <= 2^53
 
+int prepare_graph(int32_t n, const int32_t *row_ptr, const int32_t *col, HostGraph *out)
+{
+    if (!out || !row_ptr || n < 1) return HPMOCD_ERR_ARG;
+    if (row_ptr[0] != 0) return HPMOCD_ERR_RANGE;
+    for (int32_t v = 0; v < n; ++v)
+        if (row_ptr[v + 1] < row_ptr[v]) return HPMOCD_ERR_RANGE;
+    const int64_t m2 = row_ptr[n];
+    if (m2 == 0) return HPMOCD_ERR_EMPTY;
+    if (!col) return HPMOCD_ERR_ARG;
+    if (m2 > MAX_ARCS_EXACT) return HPMOCD_ERR_TOO_LARGE;
+    HostGraph &h = *out;
+    try {
+        h.rp.assign(row_ptr, row_ptr + (size_t)n + 1);
+        h.col.assign(col, col + m2);
+    } catch (...) {
+        return HPMOCD_ERR_NOMEM;
+    }
+    std::vector<int32_t> &c = h.col;
+    int32_t max_deg = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        const int32_t rs = row_ptr[v], re = row_ptr[v + 1];
+        max_deg = std::max(max_deg, re - rs);
+        for (int32_t e = rs; e < re; ++e) {
+            if (c[e] < 0 || c[e] >= n) return HPMOCD_ERR_RANGE;
+            if (c[e] == v) return HPMOCD_ERR_SELF_LOOP;
+        }
+        std::sort(c.begin() + rs, c.begin() + re);
+        for (int32_t e = rs + 1; e < re; ++e)
+            if (c[e] == c[e - 1]) return HPMOCD_ERR_DUP_EDGE;
+    }
+    for (int32_t v = 0; v < n; ++v)
+        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            const int32_t u = c[e];
+            if (!std::binary_search(c.begin() + row_ptr[u], c.begin() + row_ptr[u + 1], v))
+                return HPMOCD_ERR_CSR_ASYM;
+        }
+    // node classes for the mutation kernels (counting sort by degree)
+    try {
+        std::vector<int64_t> cnt((size_t)max_deg + 2, 0);
+        for (int32_t v = 0; v < n; ++v) ++cnt[(size_t)(row_ptr[v + 1] - row_ptr[v]) + 1];
+        for (size_t d = 1; d < cnt.size(); ++d) cnt[d] += cnt[d - 1];
+        std::vector<int32_t> by_deg(n);
+        for (int32_t v = 0; v < n; ++v) by_deg[cnt[(size_t)(row_ptr[v + 1] - row_ptr[v])]++] = v;
+        for (int32_t v : by_deg) {
+            const int32_t d = row_ptr[v + 1] - row_ptr[v];
+            if (d >= 1 && d <= SMALL_DEG_MAX) h.small.push_back(v);
+        }
+        for (auto it = by_deg.rbegin(); it != by_deg.rend(); ++it) {
+            const int32_t d = row_ptr[*it + 1] - row_ptr[*it];
+            if (d > SMALL_DEG_MAX) h.large.push_back(*it);
+        }
+    } catch (...) {
+        return HPMOCD_ERR_NOMEM;
+    }
+    h.n = n;
+    h.m2 = m2;
+    h.max_deg = max_deg;
+    for (int k = 0; k < N_DEG_CLASSES; ++k) {
+        int32_t e = 0;
+        for (int32_t v : h.small)
+            if (row_ptr[v + 1] - row_ptr[v] <= DEG_CLASS_MAX[k]) ++e;
+        h.class_end[k] = e;
+    }
+    h.large_max_deg = h.large.empty() ? 0 : row_ptr[h.large[0] + 1] - row_ptr[h.large[0]];
+    return HPMOCD_OK;
+}
+
+static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
+
+size_t graph_block_bytes(int32_t n, int64_t m2, int32_t n_small, int32_t n_large)
+{
+    return al256(4 * ((size_t)n + 1)) + al256(4 * (size_t)m2) +
+           al256(4 * std::max<size_t>(1, (size_t)n_small)) +
+           al256(4 * std::max<size_t>(1, (size_t)n_large));
+}
+
+int place_graph(const HostGraph &h, void *block, hipStream_t s, hpmocd_graph *g)
+{
+    g->n = h.n;
+    g->m2 = h.m2;
+    g->max_deg = h.max_deg;
+    g->n_small = (int32_t)h.small.size();
+    g->n_large = (int32_t)h.large.size();
+    for (int k = 0; k < N_DEG_CLASSES; ++k) g->class_end[k] = h.class_end[k];
+    g->large_max_deg = h.large_max_deg;
+    if (hipGetDevice(&g->device) != hipSuccess) return HPMOCD_ERR_HIP;
+    const size_t b_rp = 4 * ((size_t)h.n + 1), b_col = 4 * (size_t)h.m2;
+    const size_t b_small = 4 * std::max<size_t>(1, h.small.size());
+    const size_t b_large = 4 * std::max<size_t>(1, h.large.size());
+    if (block) {
+        char *p = (char *)block;
+        g->owns_device = false;
+        g->d_rp = (int32_t *)p;
+        p += al256(b_rp);
+        g->d_col = (int32_t *)p;
+        p += al256(b_col);
+        g->d_small = (int32_t *)p;
+        p += al256(b_small);
+        g->d_large = (int32_t *)p;
+        bool ok = hipMemcpyAsync(g->d_rp, h.rp.data(), b_rp, hipMemcpyHostToDevice, s) == hipSuccess;
+        ok = ok && hipMemcpyAsync(g->d_col, h.col.data(), b_col, hipMemcpyHostToDevice, s) == hipSuccess;
+        if (ok && !h.small.empty())
+            ok = hipMemcpyAsync(g->d_small, h.small.data(), 4 * h.small.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+        if (ok && !h.large.empty())
+            ok = hipMemcpyAsync(g->d_large, h.large.data(), 4 * h.large.size(), hipMemcpyHostToDevice, s) == hipSuccess;
+        return ok ? HPMOCD_OK : HPMOCD_ERR_HIP;
+    }
+    g->owns_device = true;
+    bool ok = hipMalloc(&g->d_rp, b_rp) == hipSuccess;
+    ok = ok && hipMalloc(&g->d_col, b_col) == hipSuccess;
+    ok = ok && hipMalloc(&g->d_small, b_small) == hipSuccess;
+    ok = ok && hipMalloc(&g->d_large, b_large) == hipSuccess;
+    ok = ok && hipMemcpy(g->d_rp, h.rp.data(), b_rp, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(g->d_col, h.col.data(), b_col, hipMemcpyHostToDevice) == hipSuccess;
+    if (ok && !h.small.empty())
+        ok = hipMemcpy(g->d_small, h.small.data(), 4 * h.small.size(), hipMemcpyHostToDevice) == hipSuccess;
+    if (ok && !h.large.empty())
+        ok = hipMemcpy(g->d_large, h.large.data(), 4 * h.large.size(), hipMemcpyHostToDevice) == hipSuccess;
+    return ok ? HPMOCD_OK : HPMOCD_ERR_HIP;
+}
+
 DevGraph dev_graph(const hpmocd_graph *g)
 {
     DevGraph d;
@@ -67,6 +188,8 @@ const char *hpmocd_strerror(int status)
     case HPMOCD_ERR_HIP: return "HIP runtime error";
     case HPMOCD_ERR_BUDGET: return "device-memory budget exceeded";
     case HPMOCD_ERR_NOMEM: return "host allocation failed";
+    case HPMOCD_ERR_CANCELLED: return "request cancelled";
+    case HPMOCD_ERR_TIMEOUT: return "wait timed out";
     default: return "unknown status";
     }
 }
@@ -74,83 +197,15 @@ const char *hpmocd_strerror(int status)
 int hpmocd_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *col,
                         hpmocd_graph **out)
 {
-    if (!out || !row_ptr || n < 1) return HPMOCD_ERR_ARG;
-    if (row_ptr[0] != 0) return HPMOCD_ERR_RANGE;
-    for (int32_t v = 0; v < n; ++v)
-        if (row_ptr[v + 1] < row_ptr[v]) return HPMOCD_ERR_RANGE;
-    const int64_t m2 = row_ptr[n];
-    if (m2 == 0) return HPMOCD_ERR_EMPTY;
-    if (!col) return HPMOCD_ERR_ARG;
-    if (m2 > MAX_ARCS_EXACT) return HPMOCD_ERR_TOO_LARGE;
-    std::vector<int32_t> c;
-    try {
-        c.assign(col, col + m2);
-    } catch (...) {
-        return HPMOCD_ERR_NOMEM;
-    }
-    int32_t max_deg = 0;
-    for (int32_t v = 0; v < n; ++v) {
-        const int32_t rs = row_ptr[v], re = row_ptr[v + 1];
-        max_deg = std::max(max_deg, re - rs);
-        for (int32_t e = rs; e < re; ++e) {
-            if (c[e] < 0 || c[e] >= n) return HPMOCD_ERR_RANGE;
-            if (c[e] == v) return HPMOCD_ERR_SELF_LOOP;
-        }
-        std::sort(c.begin() + rs, c.begin() + re);
-        for (int32_t e = rs + 1; e < re; ++e)
-            if (c[e] == c[e - 1]) return HPMOCD_ERR_DUP_EDGE;
-    }
-    for (int32_t v = 0; v < n; ++v)
-        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-            const int32_t u = c[e];
-            if (!std::binary_search(c.begin() + row_ptr[u], c.begin() + row_ptr[u + 1], v))
-                return HPMOCD_ERR_CSR_ASYM;
-        }
-    // node classes for the mutation kernels (counting sort by degree)
-    std::vector<int32_t> small, large;
-    {
-        std::vector<int64_t> cnt((size_t)max_deg + 2, 0);
-        for (int32_t v = 0; v < n; ++v) ++cnt[(size_t)(row_ptr[v + 1] - row_ptr[v]) + 1];
-        for (size_t d = 1; d < cnt.size(); ++d) cnt[d] += cnt[d - 1];
-        std::vector<int32_t> by_deg(n);
-        for (int32_t v = 0; v < n; ++v) by_deg[cnt[(size_t)(row_ptr[v + 1] - row_ptr[v])]++] = v;
-        for (int32_t v : by_deg) {
-            const int32_t d = row_ptr[v + 1] - row_ptr[v];
-            if (d >= 1 && d <= SMALL_DEG_MAX) small.push_back(v);
-        }
-        for (auto it = by_deg.rbegin(); it != by_deg.rend(); ++it) {
-            const int32_t d = row_ptr[*it + 1] - row_ptr[*it];
-            if (d > SMALL_DEG_MAX) large.push_back(*it);
-        }
-    }
+    if (!out) return HPMOCD_ERR_ARG;
+    HostGraph h;
+    int rc = prepare_graph(n, row_ptr, col, &h);
+    if (rc) return rc;
     hpmocd_graph *g = new (std::nothrow) hpmocd_graph;
     if (!g) return HPMOCD_ERR_NOMEM;
-    g->n = n;
-    g->m2 = m2;
-    g->max_deg = max_deg;
-    g->n_small = (int32_t)small.size();
-    g->n_large = (int32_t)large.size();
-    for (int k = 0; k < N_DEG_CLASSES; ++k) {
-        int32_t e = 0;
-        for (int32_t v : small)
-            if (row_ptr[v + 1] - row_ptr[v] <= DEG_CLASS_MAX[k]) ++e;
-        g->class_end[k] = e;
-    }
-    g->large_max_deg = large.empty() ? 0 : row_ptr[large[0] + 1] - row_ptr[large[0]];
-    bool ok = hipGetDevice(&g->device) == hipSuccess;
-    ok = ok && hipMalloc(&g->d_rp, sizeof(int32_t) * ((size_t)n + 1)) == hipSuccess;
-    ok = ok && hipMalloc(&g->d_col, sizeof(int32_t) * (size_t)m2) == hipSuccess;
-    ok = ok && hipMalloc(&g->d_small, sizeof(int32_t) * std::max<size_t>(1, small.size())) == hipSuccess;
-    ok = ok && hipMalloc(&g->d_large, sizeof(int32_t) * std::max<size_t>(1, large.size())) == hipSuccess;
-    ok = ok && hipMemcpy(g->d_rp, row_ptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyHostToDevice) == hipSuccess;
-    ok = ok && hipMemcpy(g->d_col, c.data(), sizeof(int32_t) * (size_t)m2, hipMemcpyHostToDevice) == hipSuccess;
-    if (ok && !small.empty())
-        ok = hipMemcpy(g->d_small, small.data(), sizeof(int32_t) * small.size(), hipMemcpyHostToDevice) == hipSuccess;
-    if (ok && !large.empty())
-        ok = hipMemcpy(g->d_large, large.data(), sizeof(int32_t) * large.size(), hipMemcpyHostToDevice) == hipSuccess;
-    if (!ok) {
+    if ((rc = place_graph(h, nullptr, nullptr, g))) {
         hpmocd_graph_destroy(g);
-        return HPMOCD_ERR_HIP;
+        return rc;
     }
     *out = g;
     return HPMOCD_OK;
@@ -159,6 +214,10 @@ int hpmocd_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *col,
 void hpmocd_graph_destroy(hpmocd_graph *g)
 {
     if (!g) return;
+    if (!g->owns_device) {
+        delete g;
+        return;
+    }
     if (g->d_rp) (void)hipFree(g->d_rp);
     if (g->d_col) (void)hipFree(g->d_col);
     if (g->d_small) (void)hipFree(g->d_small);

@@ -16,6 +16,7 @@ struct hpmocd_graph {
     int32_t n_small = 0, n_large = 0;
     int32_t class_end[hpm::N_DEG_CLASSES] = {};
     int32_t large_max_deg = 0;
+    bool owns_device = true;  // false when the arrays live in a server's device arena
 };
 
 namespace hpm {
@@ -25,6 +26,23 @@ namespace hpm {
         hipError_t e_ = (expr);                         \
         if (e_ != hipSuccess) return HPMOCD_ERR_HIP;    \
     } while (0)
+
+// A validated graph on the host: sorted adjacency and the mutation kernels' degree classes.
+struct HostGraph {
+    int32_t n = 0;
+    int64_t m2 = 0;
+    int32_t max_deg = 0;
+    std::vector<int32_t> rp, col, small, large;
+    int32_t class_end[N_DEG_CLASSES] = {};
+    int32_t large_max_deg = 0;
+};
+int prepare_graph(int32_t n, const int32_t *row_ptr, const int32_t *col, HostGraph *out);
+// device bytes of a graph placed in one block (each array 256-byte aligned)
+size_t graph_block_bytes(int32_t n, int64_t m2, int32_t n_small, int32_t n_large);
+// Copies the graph to the device: into `block` (graph_block_bytes, stream-ordered copies on
+// s; the host arrays must outlive them) or, with block == nullptr, into allocations of its
+// own (synchronous copies).
+int place_graph(const HostGraph &h, void *block, hipStream_t s, hpmocd_graph *g);
 
 DevGraph dev_graph(const hpmocd_graph *g);
 int check_params(const hpmocd_params *p);

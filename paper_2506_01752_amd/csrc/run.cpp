@@ -110,11 +110,16 @@ void Pop::setup(const hpmocd_graph *graph, const hpmocd_params &params, void *ws
                   both_histograms);
     c = ga_const(&p, L.ld, t.mut_target_items);
     dg = dev_graph(G);
+    shape(t, batch_nodes);
+    cur = 0;
+}
+
+void Pop::shape(const Tuning &t, int64_t batch_nodes)
+{
     const int64_t npw = batch_nodes / std::max<int64_t>(1, t.fit_target_waves);
     fit_npw = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, npw));
     const int64_t nb = batch_nodes / std::max<int64_t>(1, t.xo_target_blocks);
     xo_nb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(32, nb));
-    cur = 0;
 }
 
 Item Pop::item(int which) const

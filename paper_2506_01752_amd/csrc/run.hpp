@@ -51,6 +51,8 @@ struct Pop {
     int cur = 0;  // buffer parity: pool[cur] / q[cur] hold the current population
     void setup(const hpmocd_graph *graph, const hpmocd_params &params, void *ws, const Tuning &t,
                int64_t batch_nodes, bool both_histograms);
+    // launch shapes of this population's items for a batch of batch_nodes nodes in total
+    void shape(const Tuning &t, int64_t batch_nodes);
     Item item(int which) const;
 };
 

@@ -1,0 +1,440 @@
+// Served form: a scheduler thread that keeps many runs of Alg. 1 resident on one device and
+// advances them together (continuous batching). Each step:
+//   1. drops cancelled requests and admits queued ones in arrival order while the slot and
+//      device-byte limits hold (memory comes from a first-fit allocator over the caller's
+//      arena);
+//   2. copies the admitted graphs into their arena blocks and initialises their populations
+//      (Alg. 1 phases 1-2), then runs one generation of every resident request in shared
+//      multi-item launches, each request at its own generation and buffer parity;
+//   3. ranks the requests that have completed their T generations (phase 4), copies their
+//      fronts to the host and frees their blocks.
+// A request's arithmetic depends only on its own graph, parameters and buffers, so its front
+// is the same as in a run alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <iterator>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "host.hpp"
+#include "run.hpp"
+
+namespace hpm {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator over [0, size) with coalescing of free neighbours.
+class Arena {
+public:
+    void reset(size_t size)
+    {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto next = free_.lower_bound(off);
+        if (next != free_.end() && off + bytes == next->first) {
+            bytes += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                prev->second += bytes;
+                return;
+            }
+        }
+        free_[off] = bytes;
+    }
+
+private:
+    std::map<size_t, size_t> free_;  // offset -> length
+};
+
+struct Request {
+    int64_t ticket = 0;
+    HostGraph hg;
+    hpmocd_params p{};
+    size_t graph_bytes = 0, bytes = 0;
+    int state = HPMOCD_REQ_QUEUED;
+    int status = HPMOCD_OK;
+    bool cancel = false;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    int32_t steps = 0, max_mix = 0;
+    size_t off = 0;               // arena block (resident requests)
+    hpmocd_graph graph;           // device arrays inside the block
+    Pop pop;
+    int32_t gens_done = 0;
+    bool fresh = false;           // admitted this step: needs initialisation
+    hpmocd_front *front = nullptr;
+};
+
+}  // namespace
+}  // namespace hpm
+
+using namespace hpm;
+
+struct hpmocd_server {
+    hpmocd_server_config cfg{};
+    char *arena = nullptr;        // caller's device memory
+    size_t table_bytes = 0;       // three item tables at the start of the arena
+    hipStream_t stream = nullptr;
+    int device = 0;
+    Tuning tuning;
+    Clock::time_point epoch;
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    int broken = HPMOCD_OK;       // sticky HIP failure
+    int64_t next_ticket = 1;
+    std::map<int64_t, std::unique_ptr<Request>> reqs;
+    std::deque<Request *> queue;
+    std::vector<Request *> active;  // touched by the scheduler thread only
+    Arena alloc;
+    size_t used = 0;
+    hpmocd_server_stats stats{};
+    std::thread worker;
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - epoch).count(); }
+    void run();
+    int step(std::vector<Request *> &admitted);
+    void finish(Request *r, int status);  // caller holds mu
+};
+
+size_t hpmocd_server_arena_overhead(int32_t max_active)
+{
+    return 3 * align_up(meta_bytes(std::max(1, max_active)));
+}
+
+void hpmocd_server::finish(Request *r, int st)
+{
+    r->status = st;
+    r->state = HPMOCD_REQ_DONE;
+    r->t_done = now();
+    if (st == HPMOCD_ERR_CANCELLED)
+        ++stats.cancelled;
+    else if (st == HPMOCD_OK)
+        ++stats.completed;
+}
+
+// One scheduler step over `active` (admitted requests included, flagged fresh). Runs without
+// the lock; the stream is idle on entry and on return.
+int hpmocd_server::step(std::vector<Request *> &admitted)
+{
+    for (Request *r : admitted) {
+        int rc = place_graph(r->hg, arena + r->off, stream, &r->graph);
+        if (rc) return rc;
+        r->pop.setup(&r->graph, r->p, arena + r->off + r->graph_bytes, tuning, 1, false);
+        r->fresh = true;
+    }
+    int64_t nodes = 0;
+    for (Request *r : active) nodes += r->graph.n;
+    std::vector<Item> init_items, gen_items, final_items;
+    std::vector<Request *> gen_reqs, final_reqs;
+    for (Request *r : active) {
+        r->pop.shape(tuning, nodes);
+        if (r->fresh) init_items.push_back(r->pop.item(ITEM_INIT));
+        if (r->gens_done < r->p.generations) {
+            gen_items.push_back(r->pop.item(r->pop.cur == 0 ? ITEM_PARITY0 : ITEM_PARITY1));
+            gen_reqs.push_back(r);
+        }
+    }
+    Meta m_init, m_gen, m_final;
+    char *tables = arena;
+    const size_t tb = align_up(meta_bytes(cfg.max_active));
+    if (!init_items.empty()) {
+        int rc = m_init.upload(init_items, tables);
+        if (rc) return rc;
+        HIP_TRY(launch_init_seq(m_init, stream));
+    }
+    if (!gen_items.empty()) {
+        int rc = m_gen.upload(gen_items, tables + tb);
+        if (rc) return rc;
+        HIP_TRY(launch_generation(m_gen, stream, nullptr));
+        for (Request *r : gen_reqs) {
+            r->pop.cur = 1 - r->pop.cur;
+            ++r->gens_done;
+        }
+    }
+    for (Request *r : active) {
+        r->fresh = false;
+        ++r->steps;
+        r->max_mix = std::max<int32_t>(r->max_mix, (int32_t)active.size());
+        if (r->gens_done == r->p.generations) {
+            final_items.push_back(r->pop.item(ITEM_PARITY0));
+            final_reqs.push_back(r);
+        }
+    }
+    if (!final_items.empty()) {
+        int rc = m_final.upload(final_items, tables + 2 * tb);
+        if (rc) return rc;
+        HIP_TRY(m_final.one(ONE_FINAL, stream));
+    }
+    HIP_TRY(hipStreamSynchronize(stream));
+    for (Request *r : admitted) {  // graphs are on the device now
+        r->hg.col.clear();
+        r->hg.col.shrink_to_fit();
+        r->hg.rp.clear();
+        r->hg.rp.shrink_to_fit();
+    }
+    for (Request *r : final_reqs) {
+        int rc = extract_front(r->pop, stream, &r->front);
+        if (rc) return rc;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    for (Request *r : final_reqs) {
+        alloc.release(r->off, r->bytes);
+        used -= r->bytes;
+        finish(r, HPMOCD_OK);
+    }
+    active.erase(std::remove_if(active.begin(), active.end(),
+                                [](Request *r) { return r->state == HPMOCD_REQ_DONE; }),
+                 active.end());
+    if (!final_reqs.empty()) cv_done.notify_all();
+    return HPMOCD_OK;
+}
+
+void hpmocd_server::run()
+{
+    if (hipSetDevice(device) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(mu);
+        broken = HPMOCD_ERR_HIP;
+    }
+    for (;;) {
+        std::vector<Request *> admitted;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+            if (stop || broken) break;
+            // resident requests cancelled since the last step (the stream is idle)
+            for (Request *r : active)
+                if (r->cancel) {
+                    alloc.release(r->off, r->bytes);
+                    used -= r->bytes;
+                    finish(r, HPMOCD_ERR_CANCELLED);
+                }
+            active.erase(std::remove_if(active.begin(), active.end(),
+                                        [](Request *r) { return r->state == HPMOCD_REQ_DONE; }),
+                         active.end());
+            cv_done.notify_all();
+            while (!queue.empty() && (int32_t)active.size() < cfg.max_active &&
+                   !((cfg.flags & HPMOCD_SERVER_FIFO) && !active.empty())) {
+                Request *r = queue.front();
+                if (used + r->bytes > cfg.hbm_budget) break;  // arrival order: no overtaking
+                size_t off = 0;
+                if (!alloc.alloc(r->bytes, &off)) break;
+                queue.pop_front();
+                r->off = off;
+                used += r->bytes;
+                r->state = HPMOCD_REQ_RUNNING;
+                r->t_admit = now();
+                active.push_back(r);
+                admitted.push_back(r);
+                ++stats.admitted;
+            }
+            stats.peak_active = std::max<int32_t>(stats.peak_active, (int32_t)active.size());
+            stats.peak_bytes = std::max<int64_t>(stats.peak_bytes, (int64_t)used);
+            if (active.empty()) continue;
+        }
+        const double t0 = now();
+        int rc = step(admitted);
+        std::lock_guard<std::mutex> lk(mu);
+        stats.busy_s += now() - t0;
+        ++stats.steps;
+        if (rc) {  // a device failure ends the service: fail everything resident
+            broken = rc;
+            for (Request *r : active) {
+                used -= r->bytes;
+                finish(r, rc);
+            }
+            active.clear();
+            cv_done.notify_all();
+            break;
+        }
+    }
+    // shutdown (or failure): nothing queued will run
+    std::lock_guard<std::mutex> lk(mu);
+    (void)hipStreamSynchronize(stream);
+    for (Request *r : active) finish(r, broken ? broken : HPMOCD_ERR_CANCELLED);
+    active.clear();
+    for (Request *r : queue) finish(r, broken ? broken : HPMOCD_ERR_CANCELLED);
+    queue.clear();
+    cv_done.notify_all();
+}
+
+extern "C" {
+
+int hpmocd_server_create(const hpmocd_server_config *cfg, void *d_arena, size_t arena_bytes,
+                         void *stream, hpmocd_server **out)
+{
+    if (!cfg || !d_arena || !out) return HPMOCD_ERR_ARG;
+    if (cfg->max_active < 1 || cfg->max_active > HPMOCD_SERVER_MAX_ACTIVE) return HPMOCD_ERR_ARG;
+    if (cfg->parents_per_child < 1 || cfg->parents_per_child > HPMOCD_MAX_PARENTS)
+        return HPMOCD_ERR_ARG;
+    if (cfg->flags & ~HPMOCD_SERVER_FIFO) return HPMOCD_ERR_ARG;
+    const size_t over = hpmocd_server_arena_overhead(cfg->max_active);
+    if (arena_bytes < over || arena_bytes - over < cfg->hbm_budget || cfg->hbm_budget == 0)
+        return HPMOCD_ERR_WORKSPACE;
+    if ((uintptr_t)d_arena % 256) return HPMOCD_ERR_ARG;
+    hpmocd_server *s = new (std::nothrow) hpmocd_server;
+    if (!s) return HPMOCD_ERR_NOMEM;
+    s->cfg = *cfg;
+    s->arena = (char *)d_arena;
+    s->table_bytes = over;
+    s->stream = (hipStream_t)stream;
+    s->epoch = Clock::now();
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return HPMOCD_ERR_HIP;
+    }
+    // block offsets are relative to the arena start; the tables come first
+    s->alloc.reset(0);
+    s->alloc.release(over, arena_bytes - over);
+    try {
+        s->worker = std::thread([s] { s->run(); });
+    } catch (...) {
+        delete s;
+        return HPMOCD_ERR_NOMEM;
+    }
+    *out = s;
+    return HPMOCD_OK;
+}
+
+int hpmocd_server_submit(hpmocd_server *s, int32_t n, const int32_t *row_ptr, const int32_t *col,
+                         const hpmocd_params *p, int64_t *ticket, size_t *device_bytes)
+{
+    if (!s || !ticket) return HPMOCD_ERR_ARG;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (p->parents_per_child != s->cfg.parents_per_child) return HPMOCD_ERR_ARG;
+    std::unique_ptr<Request> r(new (std::nothrow) Request);
+    if (!r) return HPMOCD_ERR_NOMEM;
+    if ((rc = prepare_graph(n, row_ptr, col, &r->hg))) return rc;
+    r->p = *p;
+    r->graph_bytes = align_up(graph_block_bytes(r->hg.n, r->hg.m2, (int32_t)r->hg.small.size(),
+                                                (int32_t)r->hg.large.size()));
+    r->bytes = r->graph_bytes +
+               align_up(carve_run(nullptr, r->hg.n, p->pop_size, p->parents_per_child,
+                                  r->hg.max_deg, s->tuning.hist_min_log2, false)
+                            .bytes);
+    if (r->bytes > s->cfg.hbm_budget) return HPMOCD_ERR_BUDGET;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->broken) return s->broken;
+    if (s->stop) return HPMOCD_ERR_CANCELLED;
+    r->ticket = s->next_ticket++;
+    r->t_submit = s->now();
+    *ticket = r->ticket;
+    if (device_bytes) *device_bytes = r->bytes;
+    s->queue.push_back(r.get());
+    s->reqs[r->ticket] = std::move(r);
+    s->cv_work.notify_one();
+    return HPMOCD_OK;
+}
+
+int hpmocd_server_poll(hpmocd_server *s, int64_t ticket, int32_t *state)
+{
+    if (!s || !state) return HPMOCD_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return HPMOCD_ERR_ARG;
+    *state = it->second->state;
+    return HPMOCD_OK;
+}
+
+int hpmocd_server_wait(hpmocd_server *s, int64_t ticket, double timeout_s, hpmocd_front **out,
+                       hpmocd_request_info *info)
+{
+    if (!s || !out) return HPMOCD_ERR_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return HPMOCD_ERR_ARG;
+    Request *r = it->second.get();
+    auto done = [&] { return r->state == HPMOCD_REQ_DONE; };
+    if (timeout_s < 0) {
+        s->cv_done.wait(lk, done);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
+        return HPMOCD_ERR_TIMEOUT;
+    }
+    const int st = r->status;
+    if (st == HPMOCD_OK) {
+        *out = r->front;
+        r->front = nullptr;
+        if (info) {
+            info->submit_s = r->t_submit;
+            info->admit_s = r->t_admit;
+            info->done_s = r->t_done;
+            info->device_bytes = (int64_t)r->bytes;
+            info->steps = r->steps;
+            info->max_mix = r->max_mix;
+        }
+    }
+    hpmocd_front_free(r->front);
+    s->reqs.erase(it);
+    return st;
+}
+
+int hpmocd_server_cancel(hpmocd_server *s, int64_t ticket)
+{
+    if (!s) return HPMOCD_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return HPMOCD_ERR_ARG;
+    Request *r = it->second.get();
+    if (r->state == HPMOCD_REQ_QUEUED) {
+        s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
+        s->finish(r, HPMOCD_ERR_CANCELLED);
+        s->cv_done.notify_all();
+    } else if (r->state == HPMOCD_REQ_RUNNING) {
+        r->cancel = true;
+        s->cv_work.notify_one();
+    }
+    return HPMOCD_OK;
+}
+
+int hpmocd_server_stats_get(hpmocd_server *s, hpmocd_server_stats *out)
+{
+    if (!s || !out) return HPMOCD_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    return HPMOCD_OK;
+}
+
+void hpmocd_server_destroy(hpmocd_server *s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    for (auto &kv : s->reqs) hpmocd_front_free(kv.second->front);
+    delete s;
+}
+
+}  // extern "C"

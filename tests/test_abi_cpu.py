@@ -97,3 +97,30 @@ def test_no_cpu_fallback_when_library_missing(tmp_path, monkeypatch):
     monkeypatch.setattr(hp, "_lib", None)
     with pytest.raises(RuntimeError):
         hp.lib()
+
+
+def test_server_config_checks_before_any_device_call():
+    """hpmocd_server_create rejects bad configurations before touching a device."""
+    import ctypes as C
+    L = hp.lib()
+    over = L.hpmocd_server_arena_overhead(16)
+    assert over > 0 and over % 256 == 0
+    assert L.hpmocd_server_arena_overhead(4096) > over
+    h = C.c_void_p()
+    fake = C.c_void_p(1 << 20)  # never dereferenced: every case fails validation first
+
+    def create(budget, max_active, es, flags, arena):
+        cfg = hp.ServerConfig(budget, max_active, es, flags)
+        return L.hpmocd_server_create(C.byref(cfg), fake, arena, None, C.byref(h))
+
+    assert create(1 << 20, 0, 4, 0, over + (1 << 20)) == -1        # no slot
+    assert create(1 << 20, 4097, 4, 0, over + (1 << 20)) == -1     # above the slot limit
+    assert create(1 << 20, 16, 9, 0, over + (1 << 20)) == -1       # E_S above 8
+    assert create(1 << 20, 16, 4, 2, over + (1 << 20)) == -1       # unknown flag
+    assert create(1 << 20, 16, 4, 0, over + (1 << 20) - 1) == -8   # arena below budget
+    assert create(0, 16, 4, 0, over + (1 << 20)) == -8             # empty budget
+    assert L.hpmocd_server_submit(None, 1, None, None, None, None, None) == -1
+    assert L.hpmocd_server_poll(None, 1, None) == -1
+    assert L.hpmocd_server_wait(None, 1, 0.0, None, None) == -1
+    assert L.hpmocd_server_cancel(None, 1) == -1
+    L.hpmocd_server_destroy(None)
