@@ -48,8 +48,16 @@ int prepare_graph(int32_t n, const int32_t *row_ptr, const int32_t *col, HostGra
             if (!std::binary_search(c.begin() + row_ptr[u], c.begin() + row_ptr[u + 1], v))
                 return HPMOCD_ERR_CSR_ASYM;
         }
-    // node classes for the mutation kernels (counting sort by degree)
+    // upper arcs (u > v) for the fitness scan, and node classes for the mutation kernels
+    // (counting sort by degree)
     try {
+        h.up_rp.assign((size_t)n + 1, 0);
+        h.up_col.reserve((size_t)(m2 / 2));
+        for (int32_t v = 0; v < n; ++v) {
+            auto b = std::upper_bound(c.begin() + row_ptr[v], c.begin() + row_ptr[v + 1], v);
+            h.up_col.insert(h.up_col.end(), b, c.begin() + row_ptr[v + 1]);
+            h.up_rp[(size_t)v + 1] = (int32_t)h.up_col.size();
+        }
         std::vector<int64_t> cnt((size_t)max_deg + 2, 0);
         for (int32_t v = 0; v < n; ++v) ++cnt[(size_t)(row_ptr[v + 1] - row_ptr[v]) + 1];
         for (size_t d = 1; d < cnt.size(); ++d) cnt[d] += cnt[d - 1];
@@ -83,7 +91,8 @@ static size_t al256(size_t x) { return (x + 255) / 256 * 256; }
 
 size_t graph_block_bytes(int32_t n, int64_t m2, int32_t n_small, int32_t n_large)
 {
-    return al256(4 * ((size_t)n + 1)) + al256(4 * (size_t)m2) +
+    return 2 * al256(4 * ((size_t)n + 1)) + al256(4 * (size_t)m2) +
+           al256(4 * std::max<size_t>(1, (size_t)(m2 / 2))) +
            al256(4 * std::max<size_t>(1, (size_t)n_small)) +
            al256(4 * std::max<size_t>(1, (size_t)n_large));
 }
@@ -99,6 +108,7 @@ int place_graph(const HostGraph &h, void *block, hipStream_t s, hpmocd_graph *g)
     g->large_max_deg = h.large_max_deg;
     if (hipGetDevice(&g->device) != hipSuccess) return HPMOCD_ERR_HIP;
     const size_t b_rp = 4 * ((size_t)h.n + 1), b_col = 4 * (size_t)h.m2;
+    const size_t b_up = 4 * std::max<size_t>(1, h.up_col.size());
     const size_t b_small = 4 * std::max<size_t>(1, h.small.size());
     const size_t b_large = 4 * std::max<size_t>(1, h.large.size());
     if (block) {
@@ -111,8 +121,14 @@ int place_graph(const HostGraph &h, void *block, hipStream_t s, hpmocd_graph *g)
         g->d_small = (int32_t *)p;
         p += al256(b_small);
         g->d_large = (int32_t *)p;
+        p += al256(b_large);
+        g->d_up_rp = (int32_t *)p;
+        p += al256(b_rp);
+        g->d_up_col = (int32_t *)p;
         bool ok = hipMemcpyAsync(g->d_rp, h.rp.data(), b_rp, hipMemcpyHostToDevice, s) == hipSuccess;
         ok = ok && hipMemcpyAsync(g->d_col, h.col.data(), b_col, hipMemcpyHostToDevice, s) == hipSuccess;
+        ok = ok && hipMemcpyAsync(g->d_up_rp, h.up_rp.data(), b_rp, hipMemcpyHostToDevice, s) == hipSuccess;
+        ok = ok && hipMemcpyAsync(g->d_up_col, h.up_col.data(), 4 * h.up_col.size(), hipMemcpyHostToDevice, s) == hipSuccess;
         if (ok && !h.small.empty())
             ok = hipMemcpyAsync(g->d_small, h.small.data(), 4 * h.small.size(), hipMemcpyHostToDevice, s) == hipSuccess;
         if (ok && !h.large.empty())
@@ -124,7 +140,11 @@ int place_graph(const HostGraph &h, void *block, hipStream_t s, hpmocd_graph *g)
     ok = ok && hipMalloc(&g->d_col, b_col) == hipSuccess;
     ok = ok && hipMalloc(&g->d_small, b_small) == hipSuccess;
     ok = ok && hipMalloc(&g->d_large, b_large) == hipSuccess;
+    ok = ok && hipMalloc(&g->d_up_rp, b_rp) == hipSuccess;
+    ok = ok && hipMalloc(&g->d_up_col, b_up) == hipSuccess;
     ok = ok && hipMemcpy(g->d_rp, h.rp.data(), b_rp, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(g->d_up_rp, h.up_rp.data(), b_rp, hipMemcpyHostToDevice) == hipSuccess;
+    ok = ok && hipMemcpy(g->d_up_col, h.up_col.data(), 4 * h.up_col.size(), hipMemcpyHostToDevice) == hipSuccess;
     ok = ok && hipMemcpy(g->d_col, h.col.data(), b_col, hipMemcpyHostToDevice) == hipSuccess;
     if (ok && !h.small.empty())
         ok = hipMemcpy(g->d_small, h.small.data(), 4 * h.small.size(), hipMemcpyHostToDevice) == hipSuccess;
@@ -140,6 +160,8 @@ DevGraph dev_graph(const hpmocd_graph *g)
     d.m2 = g->m2;
     d.row_ptr = g->d_rp;
     d.col = g->d_col;
+    d.up_rp = g->d_up_rp;
+    d.up_col = g->d_up_col;
     d.small_nodes = g->d_small;
     d.n_small = g->n_small;
     d.large_nodes = g->d_large;
@@ -222,6 +244,8 @@ void hpmocd_graph_destroy(hpmocd_graph *g)
     if (g->d_col) (void)hipFree(g->d_col);
     if (g->d_small) (void)hipFree(g->d_small);
     if (g->d_large) (void)hipFree(g->d_large);
+    if (g->d_up_rp) (void)hipFree(g->d_up_rp);
+    if (g->d_up_col) (void)hipFree(g->d_up_col);
     delete g;
 }
 

@@ -13,6 +13,7 @@ struct hpmocd_graph {
     int32_t max_deg = 0;
     int device = 0;
     int32_t *d_rp = nullptr, *d_col = nullptr, *d_small = nullptr, *d_large = nullptr;
+    int32_t *d_up_rp = nullptr, *d_up_col = nullptr;
     int32_t n_small = 0, n_large = 0;
     int32_t class_end[hpm::N_DEG_CLASSES] = {};
     int32_t large_max_deg = 0;
@@ -33,6 +34,7 @@ struct HostGraph {
     int64_t m2 = 0;
     int32_t max_deg = 0;
     std::vector<int32_t> rp, col, small, large;
+    std::vector<int32_t> up_rp, up_col;  // neighbours u > v of each v
     int32_t class_end[N_DEG_CLASSES] = {};
     int32_t large_max_deg = 0;
 };

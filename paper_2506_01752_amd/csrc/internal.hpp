@@ -35,6 +35,9 @@ struct DevGraph {
     int64_t m2;                // 2m = number of arcs
     const int32_t *row_ptr;
     const int32_t *col;
+    // upper arcs: the neighbours u > v of every node v, ascending (each undirected edge once)
+    const int32_t *up_rp;
+    const int32_t *up_col;
     const int32_t *small_nodes;  // nodes with 1 <= deg <= SMALL_DEG_MAX, ascending degree
     int32_t n_small;
     int32_t class_end[N_DEG_CLASSES];  // end of each degree class within small_nodes

@@ -50,6 +50,8 @@ struct GGraph {
     int64_t m2;
     const GLB int32_t *row_ptr;
     const GLB int32_t *col;
+    const GLB int32_t *up_rp;
+    const GLB int32_t *up_col;
     const GLB int32_t *small_nodes;
     const GLB int32_t *large_nodes;
     int32_t n_small, n_large, large_max_deg;
@@ -61,6 +63,8 @@ __device__ __forceinline__ GGraph gview(const DevGraph &g)
     v.m2 = g.m2;
     v.row_ptr = glb(g.row_ptr);
     v.col = glb(g.col);
+    v.up_rp = glb(g.up_rp);
+    v.up_col = glb(g.up_col);
     v.small_nodes = glb(g.small_nodes);
     v.large_nodes = glb(g.large_nodes);
     v.n_small = g.n_small;
@@ -202,10 +206,11 @@ __global__ __launch_bounds__(256) void k_init(Span sp)
 
 // ---------------------------------------------------------------------------------------
 // fitness (section 4.1, eq. objectives): one wave walks a run of consecutive nodes; its
-// lanes hold two individuals each (columns 2l, 2l+1 of a 128-column chunk). For every arc
-// (v,u) the wave reads the node-major row of u once (a contiguous 8-byte-per-lane load),
-// compares with v's row and counts intra arcs per lane. v, its arc range and the neighbour
-// ids are wave-uniform (scalar loads); arcs go eight at a time, all eight loads in flight.
+// lanes hold two individuals each (columns 2l, 2l+1 of a 128-column chunk). The graph is
+// symmetric, so A (intra arcs) is twice the number of intra edges: the wave visits each
+// undirected edge once, as the upper arc (v,u) with u > v, reads the node-major row of u (a
+// contiguous 8-byte-per-lane load), compares with v's row and counts per lane; the count is
+// doubled at the end. v, its arc range and the neighbour ids are wave-uniform (scalar loads).
 // Community degree sums: D[label][col] += deg(v) by device-scope atomics whose returned
 // old value gives S exactly, since sum over the additions of (old + d)^2 - old^2 telescopes
 // to sum_c D_c^2 whatever order the atomics take.
@@ -219,9 +224,9 @@ __device__ __forceinline__ unsigned long long sq_step(int old, int d)
            (unsigned long long)(unsigned)d * (unsigned)d;
 }
 
-// Phase 1 walks the wave's arc range [row_ptr[v0], row_ptr[v1]) as one flat stream, 16 arcs
-// at a time: for each arc (s,u) it loads the rows of u and of its source s (the source row
-// is re-read from L1) and counts equal labels. Phase 2 then adds deg(v) into the histogram
+// Phase 1 walks the wave's upper-arc range [up_rp[v0], up_rp[v1]) as one flat stream, 16
+// arcs at a time: for each arc (s,u) it loads the rows of u and of its source s (the source
+// row is re-read from L1) and counts equal labels. Phase 2 then adds deg(v) into the histogram
 // for 8 nodes at a time. Keeping the histogram atomics out of phase 1 matters: vector
 // memory counters drain in order, so an atomic issued between two gathers would make the
 // second wait for the atomic's round trip.
@@ -250,8 +255,8 @@ __global__ __launch_bounds__(256) void k_fitness(Span sp)
 
     // phase 1: intra-community arcs
     int cnt0 = 0, cnt1 = 0;
-    const int32_t a0 = g.row_ptr[v0], a1 = g.row_ptr[v1];
-    int32_t src = v0, src_end = g.row_ptr[v0 + 1];
+    const int32_t a0 = g.up_rp[v0], a1 = g.up_rp[v1];
+    int32_t src = v0, src_end = g.up_rp[v0 + 1];
     for (int32_t e = a0; e < a1; e += FIT_ARCS) {
         int32_t u[FIT_ARCS], sv[FIT_ARCS];
 #pragma unroll
@@ -259,9 +264,9 @@ __global__ __launch_bounds__(256) void k_fitness(Span sp)
             const int32_t ek = min(e + k, a1 - 1);
             while (ek >= src_end) {  // uniform: advance to the arc's source node
                 ++src;
-                src_end = g.row_ptr[src + 1];
+                src_end = g.up_rp[src + 1];
             }
-            u[k] = g.col[ek];
+            u[k] = g.up_col[ek];
             sv[k] = src;
         }
         int2 x[FIT_ARCS], y[FIT_ARCS];
@@ -305,8 +310,9 @@ __global__ __launch_bounds__(256) void k_fitness(Span sp)
             s1 += sq_step(o1[k], d[k]);
         }
     }
-    gatomic_add(A + c0, (unsigned long long)cnt0);
-    if (act1) gatomic_add(A + c0 + 1, (unsigned long long)cnt1);
+    // every intra edge {v,u} stands for the two intra arcs (v,u) and (u,v)
+    gatomic_add(A + c0, 2ull * (unsigned)cnt0);
+    if (act1) gatomic_add(A + c0 + 1, 2ull * (unsigned)cnt1);
     if (atomics_phase) {
         gatomic_add(S + c0, s0);
         if (act1) gatomic_add(S + c0 + 1, s1);
