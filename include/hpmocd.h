@@ -105,6 +105,7 @@ typedef struct {
     int32_t tune_xo_target_blocks;
     int32_t tune_mut_target_items;
     int32_t tune_hist_min_log2;
+    int32_t tune_hist_rbits;
     double tune_probe_ms;      /* device time spent probing shapes (0 without autotuning) */
 } hpmocd_profile;
 

@@ -142,14 +142,23 @@ int place_graph(const HostGraph &h, void *block, hipStream_t s, hpmocd_graph *g)
     ok = ok && hipMalloc(&g->d_large, b_large) == hipSuccess;
     ok = ok && hipMalloc(&g->d_up_rp, b_rp) == hipSuccess;
     ok = ok && hipMalloc(&g->d_up_col, b_up) == hipSuccess;
-    ok = ok && hipMemcpy(g->d_rp, h.rp.data(), b_rp, hipMemcpyHostToDevice) == hipSuccess;
-    ok = ok && hipMemcpy(g->d_up_rp, h.up_rp.data(), b_rp, hipMemcpyHostToDevice) == hipSuccess;
-    ok = ok && hipMemcpy(g->d_up_col, h.up_col.data(), 4 * h.up_col.size(), hipMemcpyHostToDevice) == hipSuccess;
-    ok = ok && hipMemcpy(g->d_col, h.col.data(), b_col, hipMemcpyHostToDevice) == hipSuccess;
+    // copies on a private non-blocking stream: a null-stream copy would synchronise with
+    // (and invalidate) a hipGraph capture running in another thread
+    hipStream_t st = nullptr;
+    ok = ok && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+    ok = ok && hipMemcpyAsync(g->d_rp, h.rp.data(), b_rp, h2d, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(g->d_up_rp, h.up_rp.data(), b_rp, h2d, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(g->d_up_col, h.up_col.data(), 4 * h.up_col.size(), h2d, st) == hipSuccess;
+    ok = ok && hipMemcpyAsync(g->d_col, h.col.data(), b_col, h2d, st) == hipSuccess;
     if (ok && !h.small.empty())
-        ok = hipMemcpy(g->d_small, h.small.data(), 4 * h.small.size(), hipMemcpyHostToDevice) == hipSuccess;
+        ok = hipMemcpyAsync(g->d_small, h.small.data(), 4 * h.small.size(), h2d, st) == hipSuccess;
     if (ok && !h.large.empty())
-        ok = hipMemcpy(g->d_large, h.large.data(), 4 * h.large.size(), hipMemcpyHostToDevice) == hipSuccess;
+        ok = hipMemcpyAsync(g->d_large, h.large.data(), 4 * h.large.size(), h2d, st) == hipSuccess;
+    if (st) {
+        ok = hipStreamSynchronize(st) == hipSuccess && ok;
+        (void)hipStreamDestroy(st);
+    }
     return ok ? HPMOCD_OK : HPMOCD_ERR_HIP;
 }
 

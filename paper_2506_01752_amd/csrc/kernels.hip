@@ -146,6 +146,17 @@ __device__ __forceinline__ int item_of(const Span &sp, int &lb, int &nblk)
     return lo;
 }
 
+// Workgroups are dealt to the eight XCDs round-robin by block id, and each XCD has its own
+// L2. This renumbers an item's blocks so that the blocks one XCD runs form one contiguous
+// range of logical indices (a bijection on [0, nblk)): kernels whose neighbouring logical
+// blocks share cache lines then share them inside one L2.
+__device__ __forceinline__ int xcd_remap(int lb, int nblk)
+{
+    const int x = lb & 7, q = lb >> 3;
+    const int per = nblk >> 3, rem = nblk & 7;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + q;
+}
+
 __device__ __forceinline__ double f1_of(int64_t k1, int64_t m2) { return (double)k1 / (double)m2; }
 __device__ __forceinline__ double f2_of(int64_t k2, int64_t m2)
 {
@@ -331,18 +342,22 @@ __global__ __launch_bounds__(256) void k_fitness(Span sp)
 //   chunk into an LDS histogram of 2^rbits counters and adds sum D_c^2 to S.
 // Every addition happens in LDS; the only global atomic is one per pass-2 workgroup.
 // ---------------------------------------------------------------------------------------
-HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2)
+// largest chunk of the binned histogram (nodes per k_bin workgroup)
+constexpr int BIN_MAX_NODES = 1024;
+
+HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, int32_t max_rbits)
 {
     HistPlan p;
     int rb = 0;
-    while ((1 << rb) < n && rb < 14) ++rb;  // tiles of up to 16384 labels (64 KB of LDS)
+    const int rb_max = max_rbits < 10 ? 10 : (max_rbits > 14 ? 14 : max_rbits);
+    while ((1 << rb) < n && rb < rb_max) ++rb;  // tiles of up to 16384 labels (64 KB of LDS)
     p.rbits = rb;
     p.tiles = (int32_t)(((int64_t)n + (1 << rb) - 1) >> rb);
     const int counters = p.tiles * HB_CG;
     const int budget_words = 16384 - 64;     // 64 KB of LDS: counters, staging, scan partials
     int nb = (budget_words - counters - 1) / HB_CG;
     nb = nb / 64 * 64;
-    if (nb > 1024) nb = 1024;
+    if (nb > BIN_MAX_NODES) nb = BIN_MAX_NODES;
     p.nb = nb;
     // the plain histogram's n * pop global atomics are cheap for small problems, where the
     // two extra launches would cost more than they save
@@ -395,7 +410,9 @@ __global__ __launch_bounds__(256) void k_bin(Span sp)
     uint32_t *cnt = bl;                             // [counters + 1]
     uint32_t *stage = bl + counters + 1;            // [nb * 16]
     uint32_t *wsum = stage + (size_t)p.nb * HB_CG;  // [4]
-    const int chunk = lb % p.nchunks, grp = lb / p.nchunks;
+    // the groups of one chunk read the same label rows (16 columns each): run them together
+    const int lg = xcd_remap(lb, nblk);
+    const int chunk = lg / p.ngroups, grp = lg % p.ngroups;
     const int32_t v0 = chunk * p.nb;
     const int nv = min(p.nb, g.n - v0);
     const int cg = min(HB_CG, pop - grp * HB_CG);
@@ -410,14 +427,14 @@ __global__ __launch_bounds__(256) void k_bin(Span sp)
         bool ok[BIN_UNROLL];
 #pragma unroll
         for (int k = 0; k < BIN_UNROLL; ++k) {
-            const int it = base + k * (int)blockDim.x + (int)threadIdx.x;
-            ok[k] = it < items && (it & (HB_CG - 1)) < cg;
-            x[k] = ok[k] ? (uint32_t)lab[(size_t)(v0 + (it >> 4)) * ld + j0 + (it & (HB_CG - 1))] : 0u;
+            const int itm = base + k * (int)blockDim.x + (int)threadIdx.x;
+            ok[k] = itm < items && (itm & (HB_CG - 1)) < cg;
+            x[k] = ok[k] ? (uint32_t)lab[(size_t)(v0 + (itm >> 4)) * ld + j0 + (itm & (HB_CG - 1))] : 0u;
         }
 #pragma unroll
         for (int k = 0; k < BIN_UNROLL; ++k) {
-            const int it = base + k * (int)blockDim.x + (int)threadIdx.x;
-            if (ok[k]) atomicAdd(&cnt[(x[k] >> p.rbits) * HB_CG + (it & (HB_CG - 1))], 1u);
+            const int itm = base + k * (int)blockDim.x + (int)threadIdx.x;
+            if (ok[k]) atomicAdd(&cnt[(x[k] >> p.rbits) * HB_CG + (itm & (HB_CG - 1))], 1u);
         }
     }
     __syncthreads();
@@ -444,17 +461,17 @@ __global__ __launch_bounds__(256) void k_bin(Span sp)
         bool ok[BIN_UNROLL];
 #pragma unroll
         for (int k = 0; k < BIN_UNROLL; ++k) {
-            const int it = base + k * (int)blockDim.x + (int)threadIdx.x;
-            ok[k] = it < items && (it & (HB_CG - 1)) < cg;
-            const int32_t v = v0 + (ok[k] ? (it >> 4) : 0);
-            x[k] = ok[k] ? (uint32_t)lab[(size_t)v * ld + j0 + (it & (HB_CG - 1))] : 0u;
+            const int itm = base + k * (int)blockDim.x + (int)threadIdx.x;
+            ok[k] = itm < items && (itm & (HB_CG - 1)) < cg;
+            const int32_t v = v0 + (ok[k] ? (itm >> 4) : 0);
+            x[k] = ok[k] ? (uint32_t)lab[(size_t)v * ld + j0 + (itm & (HB_CG - 1))] : 0u;
             d[k] = (uint32_t)(g.row_ptr[v + 1] - g.row_ptr[v]);
         }
 #pragma unroll
         for (int k = 0; k < BIN_UNROLL; ++k) {
-            const int it = base + k * (int)blockDim.x + (int)threadIdx.x;
+            const int itm = base + k * (int)blockDim.x + (int)threadIdx.x;
             if (ok[k]) {
-                const uint32_t pos = atomicAdd(&cnt[(x[k] >> p.rbits) * HB_CG + (it & (HB_CG - 1))], 1u);
+                const uint32_t pos = atomicAdd(&cnt[(x[k] >> p.rbits) * HB_CG + (itm & (HB_CG - 1))], 1u);
                 stage[pos] = (x[k] & rmask) | (d[k] << p.rbits);
             }
         }
@@ -475,7 +492,9 @@ __global__ __launch_bounds__(256) void k_hist(Span sp)
     const GLB uint32_t *__restrict__ off = glb(it.off);
     GLB unsigned long long *__restrict__ S = glb(it.fit_S);
     extern __shared__ uint32_t hist[];  // [2^rbits], the whole 64 KB at most
-    const int t = lb % p.tiles, j = lb / p.tiles;
+    // individuals of one tile side by side: the 16 of a group read adjacent run offsets
+    const int lg = xcd_remap(lb, nblk);
+    const int t = lg / it.fit_pop, j = lg % it.fit_pop;
     const int grp = j / HB_CG, jl = j % HB_CG;
     const int counters = p.tiles * HB_CG;
     const int bucket = t * HB_CG + jl;

@@ -37,10 +37,10 @@ struct Carver {
 }  // namespace
 
 RunLayout carve_run(void *ws, int32_t n, int32_t pop, int32_t es, int32_t max_deg,
-                    int32_t hist_min_log2, bool both_histograms)
+                    const Tuning &t, bool both_histograms)
 {
     RunLayout L;
-    L.hp = hist_plan(n, pop, max_deg, hist_min_log2);
+    L.hp = hist_plan(n, pop, max_deg, t.hist_min_log2, t.hist_rbits);
     L.ld = round16(pop);
     L.plane = (size_t)n * (size_t)L.ld * sizeof(int32_t);
     Carver cv(ws);
@@ -50,11 +50,17 @@ RunLayout carve_run(void *ws, int32_t n, int32_t pop, int32_t es, int32_t max_de
     L.q[0] = cv.take<int32_t>(cells);
     L.q[1] = cv.take<int32_t>(cells);
     L.C = cv.take<int32_t>(cells);
-    HistPlan widest = hist_plan(n, pop, max_deg, 0);  // the binned plan, when it applies
-    if (L.hp.enabled || (both_histograms && widest.enabled)) {
-        const HistPlan &h = L.hp.enabled ? L.hp : widest;
-        L.run = cv.take<uint32_t>(h.entries);
-        L.off = cv.take<uint32_t>(h.offsets);
+    size_t entries = L.hp.enabled ? L.hp.entries : 0, offsets = L.hp.enabled ? L.hp.offsets : 0;
+    if (both_histograms)
+        for (int32_t rb : HIST_RBITS_CHOICES) {  // every binned plan the autotuner may pick
+            const HistPlan h = hist_plan(n, pop, max_deg, 0, rb);
+            if (!h.enabled) continue;
+            entries = std::max(entries, h.entries);
+            offsets = std::max(offsets, h.offsets);
+        }
+    if (entries) {
+        L.run = cv.take<uint32_t>(entries);
+        L.off = cv.take<uint32_t>(offsets);
     }
     if (!L.hp.enabled || both_histograms) L.D = cv.take<int32_t>(cells);
     DevState &s = L.st;
@@ -106,8 +112,7 @@ void Pop::setup(const hpmocd_graph *graph, const hpmocd_params &params, void *ws
 {
     G = graph;
     p = params;
-    L = carve_run(ws, G->n, p.pop_size, p.parents_per_child, G->max_deg, t.hist_min_log2,
-                  both_histograms);
+    L = carve_run(ws, G->n, p.pop_size, p.parents_per_child, G->max_deg, t, both_histograms);
     c = ga_const(&p, L.ld, t.mut_target_items);
     dg = dev_graph(G);
     shape(t, batch_nodes);
@@ -163,12 +168,14 @@ size_t meta_bytes(int32_t count)
            align_up(sizeof(int32_t) * (size_t)N_KINDS * ((size_t)count + 1));
 }
 
-int Meta::upload(const std::vector<Item> &host_items, void *region)
+int Meta::upload(const std::vector<Item> &host_items, void *region, hipStream_t s)
 {
     count = (int32_t)host_items.size();
     items = (Item *)region;
     starts = (int32_t *)((char *)region + align_up(sizeof(Item) * (size_t)count));
-    std::vector<int32_t> st((size_t)N_KINDS * ((size_t)count + 1), 0);
+    h_items = host_items;
+    h_starts.assign((size_t)N_KINDS * ((size_t)count + 1), 0);
+    std::vector<int32_t> &st = h_starts;
     for (int k = 0; k < N_KINDS; ++k) {
         int32_t *row = st.data() + (size_t)k * (count + 1);
         int64_t acc = 0;
@@ -184,8 +191,8 @@ int Meta::upload(const std::vector<Item> &host_items, void *region)
         if (acc > 0x7fffffff) return HPMOCD_ERR_ARG;
         totals[k] = (int32_t)acc;
     }
-    HIP_TRY(hipMemcpy(items, host_items.data(), sizeof(Item) * (size_t)count, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(starts, st.data(), sizeof(int32_t) * st.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpyAsync(items, h_items.data(), sizeof(Item) * (size_t)count, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(starts, st.data(), sizeof(int32_t) * st.size(), hipMemcpyHostToDevice, s));
     return HPMOCD_OK;
 }
 
@@ -276,19 +283,19 @@ int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, voi
     std::vector<int32_t> pool(plane_cells), q(plane_cells), ids(pop), rank(pop);
     std::vector<int64_t> A(pop), S(pop);
     std::vector<double> f1(pop), f2(pop), crowd(pop);
-    HIP_TRY(hipStreamSynchronize(s));
-    if (with_labels && gen > 0)
-        HIP_TRY(hipMemcpy(pool.data(), L.pool[cur], L.plane, hipMemcpyDeviceToHost));
-    if (with_labels) HIP_TRY(hipMemcpy(q.data(), L.q[cur], L.plane, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(ids.data(), L.st.ps_id, sizeof(int32_t) * pop, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(A.data(), L.st.ps_A, sizeof(int64_t) * pop, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(S.data(), L.st.ps_S, sizeof(int64_t) * pop, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(f1.data(), L.st.ps_f1, sizeof(double) * pop, hipMemcpyDeviceToHost));
-    HIP_TRY(hipMemcpy(f2.data(), L.st.ps_f2, sizeof(double) * pop, hipMemcpyDeviceToHost));
+    const hipMemcpyKind d2h = hipMemcpyDeviceToHost;
+    if (with_labels && gen > 0) HIP_TRY(hipMemcpyAsync(pool.data(), L.pool[cur], L.plane, d2h, s));
+    if (with_labels) HIP_TRY(hipMemcpyAsync(q.data(), L.q[cur], L.plane, d2h, s));
+    HIP_TRY(hipMemcpyAsync(ids.data(), L.st.ps_id, sizeof(int32_t) * pop, d2h, s));
+    HIP_TRY(hipMemcpyAsync(A.data(), L.st.ps_A, sizeof(int64_t) * pop, d2h, s));
+    HIP_TRY(hipMemcpyAsync(S.data(), L.st.ps_S, sizeof(int64_t) * pop, d2h, s));
+    HIP_TRY(hipMemcpyAsync(f1.data(), L.st.ps_f1, sizeof(double) * pop, d2h, s));
+    HIP_TRY(hipMemcpyAsync(f2.data(), L.st.ps_f2, sizeof(double) * pop, d2h, s));
     if (gen > 0) {
-        HIP_TRY(hipMemcpy(rank.data(), L.st.tr_rank, sizeof(int32_t) * pop, hipMemcpyDeviceToHost));
-        HIP_TRY(hipMemcpy(crowd.data(), L.st.tr_crowd, sizeof(double) * pop, hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemcpyAsync(rank.data(), L.st.tr_rank, sizeof(int32_t) * pop, d2h, s));
+        HIP_TRY(hipMemcpyAsync(crowd.data(), L.st.tr_crowd, sizeof(double) * pop, d2h, s));
     }
+    HIP_TRY(hipStreamSynchronize(s));
     std::vector<int32_t> rows(with_labels ? (size_t)pop * n : 0);
     for (int32_t i = 0; with_labels && i < pop; ++i) {
         const int32_t id = ids[i];
@@ -377,7 +384,7 @@ static BatchLayout batch_layout(const hpmocd_graph *const *graphs, int32_t count
         B.pop_off.push_back(off);
         off += align_up(carve_run(nullptr, graphs[i]->n, params[i].pop_size,
                                   params[i].parents_per_child, graphs[i]->max_deg,
-                                  t.hist_min_log2, both)
+                                  t, both)
                             .bytes);
     }
     for (int k = 0; k < 3; ++k) {
@@ -405,7 +412,7 @@ static int check_batch(const hpmocd_graph *const *graphs, int32_t count,
 }
 
 int Batch::setup(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_params *params,
-                 void *ws, size_t ws_bytes, const Tuning &t, bool both)
+                 void *ws, size_t ws_bytes, const Tuning &t, bool both, hipStream_t s)
 {
     tuning = t;
     BatchLayout B = batch_layout(graphs, count, params, t, both);
@@ -418,7 +425,7 @@ int Batch::setup(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_
     for (int w = 0; w < 3; ++w) {
         std::vector<Item> items;
         for (const Pop &P : pops) items.push_back(P.item(w == 0 ? ITEM_INIT : (w == 1 ? ITEM_PARITY0 : ITEM_PARITY1)));
-        int rc = meta[w].upload(items, (char *)ws + B.meta_off[w]);
+        int rc = meta[w].upload(items, (char *)ws + B.meta_off[w], s);
         if (rc) return rc;
     }
     return HPMOCD_OK;
@@ -481,7 +488,7 @@ static int autotune(const hpmocd_graph *const *graphs, int32_t count, const hpmo
     if (!a || !b) return HPMOCD_ERR_HIP;
     auto time_it = [&](const Tuning &t, double *ms) -> int {
         Batch bt;
-        int rc = bt.setup(graphs, count, probe.data(), ws, ws_bytes, t, true);
+        int rc = bt.setup(graphs, count, probe.data(), ws, ws_bytes, t, true, s);
         if (rc) return rc;
         HIP_TRY(launch_init_seq(bt.meta[0], s));
         HIP_TRY(hipEventRecord(a, s));
@@ -501,13 +508,15 @@ static int autotune(const hpmocd_graph *const *graphs, int32_t count, const hpmo
     const int32_t xo_c[] = {512, 2048, 8192};
     const int32_t mut_c[] = {48, 96, 192};
     const int32_t hist_c[] = {16, 20, 24, 31};
-    for (int knob = 0; knob < 4; ++knob) {
-        const int32_t *vals = knob == 0 ? fit_c : knob == 1 ? xo_c : knob == 2 ? mut_c : hist_c;
-        const int nv = knob == 0 ? 4 : knob == 3 ? 4 : 3;
+    for (int knob = 0; knob < 5; ++knob) {
+        const int32_t *vals = knob == 0 ? fit_c : knob == 1 ? xo_c : knob == 2 ? mut_c
+                              : knob == 3 ? hist_c : HIST_RBITS_CHOICES;
+        const int nv = knob == 0 || knob == 3 ? 4 : 3;
         for (int i = 0; i < nv; ++i) {
             Tuning t = cur;
             int32_t *field = knob == 0 ? &t.fit_target_waves : knob == 1 ? &t.xo_target_blocks
-                             : knob == 2 ? &t.mut_target_items : &t.hist_min_log2;
+                             : knob == 2 ? &t.mut_target_items
+                             : knob == 3 ? &t.hist_min_log2 : &t.hist_rbits;
             if (*field == vals[i]) continue;
             *field = vals[i];
             double ms = 0;
@@ -542,7 +551,7 @@ int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_par
     if (autotune_on && (rc = autotune(graphs, count, params, ws, ws_bytes, s, &t, &probe_ms)))
         return rc;
     Batch B;
-    if ((rc = B.setup(graphs, count, params, ws, ws_bytes, t, autotune_on))) return rc;
+    if ((rc = B.setup(graphs, count, params, ws, ws_bytes, t, autotune_on, s))) return rc;
     const bool time_kernels = (flags & HPMOCD_TIME_KERNELS) != 0 && prof;
     const bool trace_labels = (flags & HPMOCD_TRACE_NO_LABELS) == 0;
     const bool use_graph = !(flags & (HPMOCD_NO_GRAPH | HPMOCD_TIME_KERNELS)) && !trace &&
@@ -625,6 +634,7 @@ int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_par
         prof->tune_xo_target_blocks = B.tuning.xo_target_blocks;
         prof->tune_mut_target_items = B.tuning.mut_target_items;
         prof->tune_hist_min_log2 = B.tuning.hist_min_log2;
+        prof->tune_hist_rbits = B.tuning.hist_rbits;
         prof->tune_probe_ms = probe_ms;
     }
     return HPMOCD_OK;
@@ -706,7 +716,7 @@ int hpmocd_eval_workspace_size(const hpmocd_graph *g, int32_t n_ind, size_t *byt
 {
     if (!g || !bytes || n_ind < 1) return HPMOCD_ERR_ARG;
     const int32_t ld = round16(n_ind);
-    const HistPlan hp = hist_plan(g->n, n_ind, g->max_deg, Tuning{}.hist_min_log2);
+    const HistPlan hp = hist_plan(g->n, n_ind, g->max_deg, Tuning{}.hist_min_log2, Tuning{}.hist_rbits);
     size_t b = align_up((size_t)g->n * ld * 4);  // transposed labels
     b += hp.enabled ? align_up(hp.entries * 4) + align_up(hp.offsets * 4) : align_up((size_t)g->n * ld * 4);
     b += 2 * align_up(8 * (size_t)n_ind) + 2 * align_up(8 * (size_t)n_ind);
@@ -733,7 +743,7 @@ int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, v
     p += align_up(plane);
     Item it{};
     it.g = dev_graph(G);
-    it.hp = hist_plan(G->n, n_ind, G->max_deg, Tuning{}.hist_min_log2);
+    it.hp = hist_plan(G->n, n_ind, G->max_deg, Tuning{}.hist_min_log2, Tuning{}.hist_rbits);
     if (it.hp.enabled) {
         it.run = (uint32_t *)p;
         p += align_up(it.hp.entries * 4);
@@ -763,7 +773,7 @@ int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, v
     it.c.pop = n_ind;
     Meta m;
     std::vector<Item> items(1, it);
-    if ((rc = m.upload(items, p))) return rc;
+    if ((rc = m.upload(items, p, s))) return rc;
     HIP_TRY(m.launch(K_CLEAR, s));
     HIP_TRY(m.one(ONE_ZERO_ACC, s));
     HIP_TRY(launch_transpose_in(d_labels, G->n, n_ind, ld, lab, s));

@@ -19,7 +19,11 @@ struct Tuning {
     int32_t xo_target_blocks = 2048;   // crossover/init workgroups wanted over the batch
     int32_t mut_target_items = 96;     // mutations queued per wave group (small degrees)
     int32_t hist_min_log2 = 20;        // binned histogram from 2^k (node, individual) pairs
+    int32_t hist_rbits = 14;           // binned histogram tiles of up to 2^k labels
 };
+
+// tile sizes (log2 labels per tile) the autotuner tries for the binned histogram
+constexpr int32_t HIST_RBITS_CHOICES[3] = {12, 13, 14};
 
 struct RunLayout {
     int32_t ld = 0;
@@ -34,8 +38,10 @@ struct RunLayout {
     size_t bytes = 0;
 };
 
+// both_histograms: room for the plain plane and for the binned areas of every tile size the
+// autotuner may try
 RunLayout carve_run(void *ws, int32_t n, int32_t pop, int32_t es, int32_t max_deg,
-                    int32_t hist_min_log2, bool both_histograms);
+                    const Tuning &t, bool both_histograms);
 GaConst ga_const(const hpmocd_params *p, int32_t ld, int32_t mut_target);
 
 enum ItemWhich { ITEM_INIT = 0, ITEM_PARITY0, ITEM_PARITY1 };
@@ -57,7 +63,12 @@ struct Pop {
 };
 
 // Device tables of one set of items: the items and, per launch kind, the block offsets.
+// upload() copies them on the given stream (never the null stream, which would synchronise
+// with, and break, a hipGraph capture in another thread); the host copies stay in the Meta,
+// so it must outlive the copies (the stream is synchronised before a Meta goes away).
 struct Meta {
+    std::vector<Item> h_items;
+    std::vector<int32_t> h_starts;
     Item *items = nullptr;
     int32_t *starts = nullptr;
     int32_t count = 0;
@@ -65,7 +76,7 @@ struct Meta {
     size_t lds[N_KINDS] = {};
     int32_t aux[N_KINDS] = {};
     Span span(Kind k) const { return Span{items, starts + (size_t)k * (count + 1), count}; }
-    int upload(const std::vector<Item> &host_items, void *region);
+    int upload(const std::vector<Item> &host_items, void *region, hipStream_t s);
     hipError_t launch(Kind k, hipStream_t s) const;
     hipError_t one(OneKernel which, hipStream_t s) const;
 };
@@ -93,7 +104,7 @@ struct Batch {
     Meta meta[3];  // init, parity 0, parity 1
     Tuning tuning;
     int setup(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_params *params,
-              void *ws, size_t ws_bytes, const Tuning &t, bool both);
+              void *ws, size_t ws_bytes, const Tuning &t, bool both, hipStream_t s);
     int generations(int32_t first, int32_t last, hipStream_t s, bool use_graph,
                     std::vector<std::vector<EventPair>> *ev, hpmocd_trace_fn trace, void *user,
                     bool trace_labels);

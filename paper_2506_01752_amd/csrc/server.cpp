@@ -168,12 +168,12 @@ int hpmocd_server::step(std::vector<Request *> &admitted)
     char *tables = arena;
     const size_t tb = align_up(meta_bytes(cfg.max_active));
     if (!init_items.empty()) {
-        int rc = m_init.upload(init_items, tables);
+        int rc = m_init.upload(init_items, tables, stream);
         if (rc) return rc;
         HIP_TRY(launch_init_seq(m_init, stream));
     }
     if (!gen_items.empty()) {
-        int rc = m_gen.upload(gen_items, tables + tb);
+        int rc = m_gen.upload(gen_items, tables + tb, stream);
         if (rc) return rc;
         HIP_TRY(launch_generation(m_gen, stream, nullptr));
         for (Request *r : gen_reqs) {
@@ -191,7 +191,7 @@ int hpmocd_server::step(std::vector<Request *> &admitted)
         }
     }
     if (!final_items.empty()) {
-        int rc = m_final.upload(final_items, tables + 2 * tb);
+        int rc = m_final.upload(final_items, tables + 2 * tb, stream);
         if (rc) return rc;
         HIP_TRY(m_final.one(ONE_FINAL, stream));
     }
@@ -340,7 +340,7 @@ int hpmocd_server_submit(hpmocd_server *s, int32_t n, const int32_t *row_ptr, co
                                                 (int32_t)r->hg.large.size()));
     r->bytes = r->graph_bytes +
                align_up(carve_run(nullptr, r->hg.n, p->pop_size, p->parents_per_child,
-                                  r->hg.max_deg, s->tuning.hist_min_log2, false)
+                                  r->hg.max_deg, s->tuning, false)
                             .bytes);
     if (r->bytes > s->cfg.hbm_budget) return HPMOCD_ERR_BUDGET;
     std::lock_guard<std::mutex> lk(s->mu);
