@@ -185,7 +185,7 @@ int hpmocd_eval(const hpmocd_graph *g, const int32_t *d_labels, int32_t n_ind,
  * of a server share parents_per_child (one crossover kernel shape per step). */
 typedef struct hpmocd_server hpmocd_server;
 
-#define HPMOCD_SERVER_FIFO 1          /* baseline: admit only when no request is resident */
+#define HPMOCD_SERVER_FIFO 1  /* baseline: one request at a time, each run as hpmocd_run */
 #define HPMOCD_SERVER_MAX_ACTIVE 4096
 
 typedef struct {

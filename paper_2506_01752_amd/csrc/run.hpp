@@ -99,6 +99,13 @@ int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, voi
                bool with_labels);
 int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out);
 
+// A whole batched run (init, T generations, fronts); a single run is a batch of one.
+int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_params *params,
+              void *ws, size_t ws_bytes, void *stream, int flags, hpmocd_profile *prof,
+              hpmocd_trace_fn trace, void *user, hpmocd_front **outs);
+size_t batch_workspace(const hpmocd_graph *const *graphs, int32_t count,
+                       const hpmocd_params *params, bool both);
+
 struct Batch {
     std::vector<Pop> pops;
     Meta meta[3];  // init, parity 0, parity 1

@@ -146,6 +146,25 @@ void hpmocd_server::finish(Request *r, int st)
 // the lock; the stream is idle on entry and on return.
 int hpmocd_server::step(std::vector<Request *> &admitted)
 {
+    if (cfg.flags & HPMOCD_SERVER_FIFO) {  // baseline: the one resident request as a plain run
+        Request *r = active.front();
+        int rc = place_graph(r->hg, arena + r->off, stream, &r->graph);
+        if (rc) return rc;
+        const hpmocd_graph *gp = &r->graph;
+        rc = run_batch(&gp, 1, &r->p, arena + r->off + r->graph_bytes, r->bytes - r->graph_bytes,
+                       stream, 0, nullptr, nullptr, nullptr, &r->front);
+        if (rc) return rc;  // run_batch returns with the stream drained
+        r->hg = HostGraph();
+        r->steps = 1;
+        r->max_mix = 1;
+        std::lock_guard<std::mutex> lk(mu);
+        alloc.release(r->off, r->bytes);
+        used -= r->bytes;
+        finish(r, HPMOCD_OK);
+        active.clear();
+        cv_done.notify_all();
+        return HPMOCD_OK;
+    }
     for (Request *r : admitted) {
         int rc = place_graph(r->hg, arena + r->off, stream, &r->graph);
         if (rc) return rc;
@@ -338,10 +357,18 @@ int hpmocd_server_submit(hpmocd_server *s, int32_t n, const int32_t *row_ptr, co
     r->p = *p;
     r->graph_bytes = align_up(graph_block_bytes(r->hg.n, r->hg.m2, (int32_t)r->hg.small.size(),
                                                 (int32_t)r->hg.large.size()));
-    r->bytes = r->graph_bytes +
-               align_up(carve_run(nullptr, r->hg.n, p->pop_size, p->parents_per_child,
-                                  r->hg.max_deg, s->tuning, false)
-                            .bytes);
+    if (s->cfg.flags & HPMOCD_SERVER_FIFO) {  // a plain run's workspace
+        hpmocd_graph shape;
+        shape.n = r->hg.n;
+        shape.max_deg = r->hg.max_deg;
+        const hpmocd_graph *gp = &shape;
+        r->bytes = r->graph_bytes + align_up(batch_workspace(&gp, 1, p, false));
+    } else {
+        r->bytes = r->graph_bytes +
+                   align_up(carve_run(nullptr, r->hg.n, p->pop_size, p->parents_per_child,
+                                      r->hg.max_deg, s->tuning, false)
+                                .bytes);
+    }
     if (r->bytes > s->cfg.hbm_budget) return HPMOCD_ERR_BUDGET;
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->broken) return s->broken;
