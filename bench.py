@@ -145,6 +145,56 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_quality(args):
+    """Not a speed figure: how well the selected solution (Alg. 3) recovers the planted
+    communities, against the best partition of the initial population."""
+    import numpy as np
+    import torch
+
+    import paper_2506_01752_amd as hp
+    from paper_2506_01752_amd import quality as q
+    import synth
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+
+    def one(g, seed):
+        dg = hp.Graph(g.row_ptr, g.col)
+        init = {}
+
+        def cb(st):
+            if st.g == 0:
+                init["labels"] = st.labels
+        front = hp.run(dg, stream=stream, on_generation=cb,
+                       **dict(synth.GA_DEFAULT, seed=seed))
+        sel = front.labels[front.selected]
+        best0 = max(q.nmi(row, g.membership) for row in init["labels"])
+        return {"nmi": q.nmi(sel, g.membership), "ari": q.ari(sel, g.membership),
+                "pair_f1": q.pair_f1(sel, g.membership),
+                "q": q.modularity(front.f1[front.selected], front.f2[front.selected]),
+                "front_size": int(front.labels.shape[0]),
+                "front_best_nmi": max(q.nmi(r, g.membership) for r in front.labels),
+                "communities_found": int(len(np.unique(sel))),
+                "communities_planted": int(len(np.unique(g.membership))),
+                "init_best_nmi": best0}
+
+    out = {"small_1k_mu0.3": [], "mid_40k": {}}
+    g1 = synth.small_1k()
+    for seed in range(5):
+        out["small_1k_mu0.3"].append(one(g1, seed))
+        print(f"# 1k seed {seed}: {out['small_1k_mu0.3'][-1]}", file=sys.stderr, flush=True)
+    for mu in (0.1, 0.3, 0.5, 0.7):
+        g = synth.mid_40k(mu)
+        out["mid_40k"][f"mu{mu}"] = dict(one(g, 0), realised_mu=g.info["realised_mu"])
+        print(f"# 40k mu {mu}: {out['mid_40k'][f'mu{mu}']}", file=sys.stderr, flush=True)
+    nm = [r["nmi"] for r in out["small_1k_mu0.3"]]
+    print(json.dumps({"metric": "solution quality (NMI of the selected solution vs planted)",
+                      "value": float(np.mean(nm)), "unit": "NMI", "n_gpus": 1,
+                      "higher_is_better": True, "data": "synthetic",
+                      "config": {"workload": "quality_1k_and_40k_mu_sweep"},
+                      "nmi_1k_std_over_seeds": float(np.std(nm)), "detail": out}), flush=True)
+
+
 def _request_graph(p):
     import synth
     g = synth.batch_graph(p)
@@ -290,6 +340,10 @@ def main():
                     help="served form instead: COUNT requests (|V| log-uniform in [1000, 200000], "
                          "pop 100, 100 generations) arriving as a Poisson stream, continuous "
                          "batching vs plain FIFO")
+    ap.add_argument("--quality", action="store_true",
+                    help="solution-quality sanity instead: agreement of the selected solution "
+                         "with the planted partition at |V| = 1,000 (5 seeds) and |V| = 40,000 "
+                         "(mu sweep)")
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -314,6 +368,8 @@ def main():
         return bench_batched(args)
     if args.served:
         return bench_served(args)
+    if args.quality:
+        return bench_quality(args)
 
     import torch
 

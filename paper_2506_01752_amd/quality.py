@@ -1,0 +1,75 @@
+"""Agreement between a found partition and a reference partition (section 5's evaluation
+measures): normalised mutual information, adjusted Rand index and pair-counting F1, plus the
+modularity of a front point. Host-side numpy; these are reporting tools, not the search.
+
+Partitions are integer label arrays of equal length; label values are arbitrary names.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _contingency(a, b):
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    if a.shape != b.shape:
+        raise ValueError("partitions of different sizes")
+    _, ia = np.unique(a, return_inverse=True)
+    _, ib = np.unique(b, return_inverse=True)
+    ka, kb = ia.max() + 1, ib.max() + 1
+    cell = np.bincount(ia.astype(np.int64) * kb + ib, minlength=ka * kb).reshape(ka, kb)
+    return cell.astype(np.float64)
+
+
+def _entropy(counts, n):
+    p = counts[counts > 0] / n
+    return float(-(p * np.log(p)).sum())
+
+
+def nmi(a, b) -> float:
+    """Mutual information over the arithmetic mean of the two entropies (1 for equal
+    partitions up to renaming; 1 also when both are a single community)."""
+    c = _contingency(a, b)
+    n = c.sum()
+    ha, hb = _entropy(c.sum(1), n), _entropy(c.sum(0), n)
+    if ha == 0.0 and hb == 0.0:
+        return 1.0
+    nz = c > 0
+    pij = c[nz] / n
+    pa = (c.sum(1, keepdims=True) / n * np.ones_like(c))[nz]
+    pb = (c.sum(0, keepdims=True) / n * np.ones_like(c))[nz]
+    mi = float((pij * np.log(pij / (pa * pb))).sum())
+    return max(0.0, mi / (0.5 * (ha + hb)))
+
+
+def _pairs(x):
+    return x * (x - 1) / 2.0
+
+
+def ari(a, b) -> float:
+    """Adjusted Rand index (Hubert and Arabie)."""
+    c = _contingency(a, b)
+    n = c.sum()
+    s_ij = _pairs(c).sum()
+    s_a, s_b = _pairs(c.sum(1)).sum(), _pairs(c.sum(0)).sum()
+    expected = s_a * s_b / _pairs(n) if n > 1 else 0.0
+    top = 0.5 * (s_a + s_b)
+    if top == expected:
+        return 1.0
+    return float((s_ij - expected) / (top - expected))
+
+
+def pair_f1(found, truth) -> float:
+    """F1 over node pairs: a pair is positive when both nodes share a community."""
+    c = _contingency(found, truth)
+    tp = _pairs(c).sum()
+    pos_found = _pairs(c.sum(1)).sum()
+    pos_truth = _pairs(c.sum(0)).sum()
+    if pos_found == 0 and pos_truth == 0:
+        return 1.0
+    return float(2 * tp / (pos_found + pos_truth))
+
+
+def modularity(f1: float, f2: float) -> float:
+    """Q = (1 - f1) - f2 (Alg. 3's selection criterion, eq. modularity)."""
+    return (1.0 - f1) - f2
