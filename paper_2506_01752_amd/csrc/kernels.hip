@@ -393,7 +393,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *w
     return base + x - v;
 }
 
-constexpr int BIN_UNROLL = 16;
+constexpr int BIN_UNROLL = 32;
 
 __global__ __launch_bounds__(256) void k_bin(Span sp)
 {
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) void k_bin(Span sp)
     for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) dst[i] = stage[i];
 }
 
-constexpr int HIST_UNROLL = 8;
+constexpr int HIST_UNROLL = 16;
 
 __global__ __launch_bounds__(256) void k_hist(Span sp)
 {
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(256) void k_hist(Span sp)
     __syncthreads();
     const size_t span = (size_t)p.nb * HB_CG;
     // each thread owns chunks w = tid + 256 k; the run bounds of up to 8 of them are loaded
-    // together, then the runs are read 8 words at a time
+    // together, then the runs are read HIST_UNROLL words at a time
     constexpr int WPT = 8;
     for (int w0 = 0; w0 < p.nchunks; w0 += (int)blockDim.x * WPT) {
         uint32_t b0[WPT], b1[WPT];
