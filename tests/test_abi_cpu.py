@@ -124,3 +124,14 @@ def test_server_config_checks_before_any_device_call():
     assert L.hpmocd_server_wait(None, 1, 0.0, None, None) == -1
     assert L.hpmocd_server_cancel(None, 1) == -1
     L.hpmocd_server_destroy(None)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py --gpus N (N > 1) exits with a message instead of running (one-GPU build)."""
+    import json
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["n_gpus"] == 2 and "one GPU" in line["error"]

@@ -189,3 +189,33 @@ def test_deterministic_repeat(hp, stream):
     a = hp.run(dg, stream=stream, pop_size=40, generations=12, seed=1)
     b = hp.run(dg, stream=stream, pop_size=40, generations=12, seed=1)
     assert_front_equal(a, b)
+
+
+def test_single_edge_and_many_components(hp, stream):
+    """Smallest graph (one edge) and a forest of small components with isolated nodes."""
+    k2 = synth.csr_from_edges(2, [(0, 1)])
+    rng = np.random.default_rng(4)
+    edges = []
+    for c in range(30):  # 30 small trees of 2-6 nodes, then 40 isolated nodes
+        base = 6 * c
+        size = int(rng.integers(2, 7))
+        edges += [(base + i, base + int(rng.integers(0, i))) for i in range(1, size)]
+    forest = synth.csr_from_edges(220, edges)
+    for name, g in [("k2", k2), ("forest", forest)]:
+        say(f"run {name} n={g.n} m={g.m}")
+        got, ref, gs, os_ = traced_pair(hp, stream, g, pop_size=12, generations=6, seed=8,
+                                        mutation_p=0.5)
+        assert_states_equal(gs, os_)
+        assert_front_equal(got, ref)
+
+
+@pytest.mark.parametrize("pop", [16, 17])
+def test_binned_histogram_small_population_1m(hp, stream, pop):
+    """|V| = 1,000,000 with 16 and 17 individuals (one and two 16-column histogram groups,
+    row strides 16 and 32): every generation against the oracle."""
+    g = synth.large_1m()
+    say(f"run large_1m pop={pop}")
+    got, ref, gs, os_ = traced_pair(hp, stream, g, threads=8, pop_size=pop, generations=2,
+                                    seed=21)
+    assert_states_equal(gs, os_)
+    assert_front_equal(got, ref)
