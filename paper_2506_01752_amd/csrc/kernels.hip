@@ -1215,6 +1215,19 @@ __device__ __forceinline__ int wave_plurality(const GLB int32_t *__restrict__ C,
 
 // Degree class (64(E/2), 64E]: a wave per node draws the MUT words of all offspring, queues
 // the mutating ones in LDS and resolves them one at a time with the wave sort.
+// Waves per node in the wave classes: a node's offspring are split into this many slices so
+// that one wave resolves about `per` mutations (a node has pop * M_P of them on average). One
+// wave per node left the few high-degree nodes' waves resolving ten or more wave-wide sorts
+// one after another while the rest of the chip idled.
+__host__ __device__ inline int mut_slices(int cls, int pop, uint64_t thr_m)
+{
+    if (cls < 2) return 1;
+    const int per = cls == 2 ? 8 : (cls == 3 ? 4 : (cls == 4 ? 2 : 1));
+    const int expect = (int)(((uint64_t)pop * thr_m) >> 32);  // floor(pop * M_P)
+    const int sl = expect / per;
+    return sl < 1 ? 1 : (sl > pop ? pop : sl);
+}
+
 template <int E>
 __global__ __launch_bounds__(256) void k_mutate_wave(Span sp, int cls)
 {
@@ -1232,17 +1245,21 @@ __global__ __launch_bounds__(256) void k_mutate_wave(Span sp, int cls)
     const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = lane_id();
     const uint32_t gen = (uint32_t)*st.gen;
     const int pop = c.pop, ld = c.ld;
-    for (int t = lb * MUT_WAVES + wv; t < count_nodes; t += nblk * MUT_WAVES) {
-        const int32_t node = list[t];
+    const int slices = mut_slices(cls, pop, c.thr_m);
+    const int span = (pop + slices - 1) / slices;
+    const int units = count_nodes * slices;  // (node, slice of its offspring)
+    for (int t = lb * MUT_WAVES + wv; t < units; t += nblk * MUT_WAVES) {
+        const int32_t node = list[t / slices];
+        const int jlo = (t % slices) * span, jhi = min(pop, jlo + span);
         const int32_t rs = g.row_ptr[node];
         const int d = g.row_ptr[node + 1] - rs;
         const GLB int32_t *nbr = g.col + rs;
         int count = 0;
-        for (int j0 = 0; j0 < pop; j0 += 64) {
+        for (int j0 = jlo; j0 < jhi; j0 += 64) {
             const int j = j0 + lane;
             bool mut = false;
             uint32_t r = 0;
-            if (j < pop) {
+            if (j < jhi) {
                 const u32x4 w = philox(c.seed, (uint32_t)node, (uint32_t)j, gen, TAG_MUT);
                 mut = (uint64_t)w.a < c.thr_m;
                 r = w.b;
@@ -1538,7 +1555,7 @@ int32_t kind_blocks(Kind k, const Item &it)
         const int32_t b = ceil_div(ceil_div(cnt, it.c.mut_group), MUT_WAVES);
         return b > 8192 ? 8192 : b;
     }
-    const int32_t b = ceil_div(cnt, MUT_WAVES);
+    const int32_t b = ceil_div((int64_t)cnt * mut_slices(cls, it.c.pop, it.c.thr_m), MUT_WAVES);
     return b > 16384 ? 16384 : b;
 }
 

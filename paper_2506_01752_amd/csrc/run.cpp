@@ -225,7 +225,53 @@ hipError_t launch_init_seq(const Meta &m, hipStream_t s)
     return m.one(ONE_INIT_STATE, s);
 }
 
-hipError_t launch_generation(const Meta &m, hipStream_t s, const EventPair *ev)
+int Fork::init()
+{
+    for (int i = 0; i < 2; ++i) {
+        if (!side[i]) HIP_TRY(hipStreamCreateWithFlags(&side[i], hipStreamNonBlocking));
+        if (!join[i]) HIP_TRY(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
+    }
+    if (!fork) HIP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    return HPMOCD_OK;
+}
+
+Fork::~Fork()
+{
+    for (int i = 0; i < 2; ++i) {
+        if (side[i]) (void)hipStreamDestroy(side[i]);
+        if (join[i]) (void)hipEventDestroy(join[i]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
+}
+
+// Mutation launches of one generation. With a fork: degree classes <= 16 and 513-1024 on s,
+// 17-32, 33-64 and 257-512 on the first side stream, the rest on the second (a rough split
+// of their measured times), joined back into s.
+static hipError_t launch_mutation(const Meta &m, hipStream_t s, const Fork *fk)
+{
+    hipError_t e;
+    if (!fk) {
+        for (int k = 0; k < N_DEG_CLASSES; ++k)
+            if ((e = m.launch((Kind)(K_MUT0 + k), s)) != hipSuccess) return e;
+        return m.launch(K_MUTL, s);
+    }
+    static const int group[N_DEG_CLASSES] = {0, 1, 1, 2, 2, 1, 0, 2};
+    if ((e = hipEventRecord(fk->fork, s)) != hipSuccess) return e;
+    for (int i = 0; i < 2; ++i)
+        if ((e = hipStreamWaitEvent(fk->side[i], fk->fork, 0)) != hipSuccess) return e;
+    for (int k = 0; k < N_DEG_CLASSES; ++k) {
+        hipStream_t st = group[k] == 0 ? s : fk->side[group[k] - 1];
+        if ((e = m.launch((Kind)(K_MUT0 + k), st)) != hipSuccess) return e;
+    }
+    if ((e = m.launch(K_MUTL, fk->side[1])) != hipSuccess) return e;
+    for (int i = 0; i < 2; ++i) {
+        if ((e = hipEventRecord(fk->join[i], fk->side[i])) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, fk->join[i], 0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_generation(const Meta &m, hipStream_t s, const EventPair *ev, const Fork *fk)
 {
     hipError_t e;
     auto mark = [&](int k, bool end) {
@@ -236,9 +282,7 @@ hipError_t launch_generation(const Meta &m, hipStream_t s, const EventPair *ev)
     mark(0, true);
     mark(1, false);
     if ((e = m.launch(K_XO, s)) != hipSuccess) return e;
-    for (int k = 0; k < N_DEG_CLASSES; ++k)
-        if ((e = m.launch((Kind)(K_MUT0 + k), s)) != hipSuccess) return e;
-    if ((e = m.launch(K_MUTL, s)) != hipSuccess) return e;
+    if ((e = launch_mutation(m, s, fk)) != hipSuccess) return e;
     mark(1, true);
     mark(2, false);
     if ((e = launch_fitness_kinds(m, s)) != hipSuccess) return e;
@@ -415,6 +459,7 @@ int Batch::setup(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_
                  void *ws, size_t ws_bytes, const Tuning &t, bool both, hipStream_t s)
 {
     tuning = t;
+    if (int rc = fork.init()) return rc;
     BatchLayout B = batch_layout(graphs, count, params, t, both);
     if (ws_bytes < B.bytes) return HPMOCD_ERR_WORKSPACE;
     int64_t total_nodes = 0;
@@ -443,8 +488,8 @@ int Batch::generations(int32_t first, int32_t last, hipStream_t s, bool use_grap
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        hipError_t e1 = launch_generation(meta[1 + p0], s, nullptr);
-        hipError_t e2 = e1 == hipSuccess ? launch_generation(meta[1 + (1 - p0)], s, nullptr) : e1;
+        hipError_t e1 = launch_generation(meta[1 + p0], s, nullptr, &fork);
+        hipError_t e2 = e1 == hipSuccess ? launch_generation(meta[1 + (1 - p0)], s, nullptr, &fork) : e1;
         hipError_t ec = hipStreamEndCapture(s, &graph);
         if (e1 != hipSuccess || e2 != hipSuccess || ec != hipSuccess) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -463,7 +508,7 @@ int Batch::generations(int32_t first, int32_t last, hipStream_t s, bool use_grap
     for (; gen <= last; ++gen) {
         const int par = pops.empty() ? 0 : pops[0].cur;
         const EventPair *evp = ev ? (*ev)[(size_t)(gen - 1)].data() : nullptr;
-        HIP_TRY(launch_generation(meta[1 + par], s, evp));
+        HIP_TRY(launch_generation(meta[1 + par], s, evp, &fork));
         for (Pop &P : pops) P.cur = 1 - P.cur;
         if (trace) {
             int rc = emit_state(pops[0], gen, s, trace, user, trace_labels);

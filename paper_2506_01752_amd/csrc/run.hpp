@@ -92,9 +92,24 @@ struct EventSet {
 };
 float elapsed(hipEvent_t a, hipEvent_t b);
 
+// Two side streams and their events: the mutation classes touch disjoint nodes, so they run
+// as parallel branches of the generation (bandwidth-bound per-lane classes beside
+// latency-bound per-wave classes); inside a hipGraph capture they become parallel nodes.
+// Streams at the default priority.
+struct Fork {
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    int init();
+    Fork() = default;
+    Fork(const Fork &) = delete;
+    Fork &operator=(const Fork &) = delete;
+    ~Fork();
+};
+
 hipError_t launch_fitness_kinds(const Meta &m, hipStream_t s);
 hipError_t launch_init_seq(const Meta &m, hipStream_t s);
-hipError_t launch_generation(const Meta &m, hipStream_t s, const EventPair *ev);
+// fk == nullptr: every kernel on s, one after another
+hipError_t launch_generation(const Meta &m, hipStream_t s, const EventPair *ev, const Fork *fk);
 int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, void *user,
                bool with_labels);
 int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out);
@@ -110,6 +125,7 @@ struct Batch {
     std::vector<Pop> pops;
     Meta meta[3];  // init, parity 0, parity 1
     Tuning tuning;
+    Fork fork;
     int setup(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_params *params,
               void *ws, size_t ws_bytes, const Tuning &t, bool both, hipStream_t s);
     int generations(int32_t first, int32_t last, hipStream_t s, bool use_graph,

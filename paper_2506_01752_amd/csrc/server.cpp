@@ -105,6 +105,7 @@ struct hpmocd_server {
     hipStream_t stream = nullptr;
     int device = 0;
     Tuning tuning;
+    Fork fork;  // side streams of the mutation classes
     Clock::time_point epoch;
 
     std::mutex mu;
@@ -194,7 +195,7 @@ int hpmocd_server::step(std::vector<Request *> &admitted)
     if (!gen_items.empty()) {
         int rc = m_gen.upload(gen_items, tables + tb, stream);
         if (rc) return rc;
-        HIP_TRY(launch_generation(m_gen, stream, nullptr));
+        HIP_TRY(launch_generation(m_gen, stream, nullptr, &fork));
         for (Request *r : gen_reqs) {
             r->pop.cur = 1 - r->pop.cur;
             ++r->gens_done;
@@ -327,7 +328,7 @@ int hpmocd_server_create(const hpmocd_server_config *cfg, void *d_arena, size_t 
     s->table_bytes = over;
     s->stream = (hipStream_t)stream;
     s->epoch = Clock::now();
-    if (hipGetDevice(&s->device) != hipSuccess) {
+    if (hipGetDevice(&s->device) != hipSuccess || s->fork.init() != HPMOCD_OK) {
         delete s;
         return HPMOCD_ERR_HIP;
     }
