@@ -436,7 +436,7 @@ def main():
         "variation_ms_per_gen": sum(p["variation_ms"] for p in profs) / max(1, T * args.steps),
         "select_ms_per_gen": sum(p["select_ms"] for p in profs) / max(1, T * args.steps),
         "population_floor_GBps": population_floor_bytes(g.n, 2 * g.m, pop) / (eval_ms / 1e3) / 1e9,
-        "roofline": {"bound": "hbm", "kernel": "fitness (k_fitness + k_bin + k_hist)",
+        "roofline": {"bound": "hbm", "kernel": "fitness step (k_bin, then k_fitness beside k_hist)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": measured_traffic(args.workload, pop),

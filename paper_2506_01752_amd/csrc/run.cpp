@@ -206,21 +206,38 @@ hipError_t Meta::one(OneKernel which, hipStream_t s) const
     return launch_one(which, span(K_ONE), count, s);
 }
 
-hipError_t launch_fitness_kinds(const Meta &m, hipStream_t s)
+// Fitness of a population. k_fitness (A) only reads the labels, so with a fork it runs
+// beside k_hist: k_bin first (bandwidth-bound, like the arc scan), then the arc scan on a
+// side stream next to k_hist, whose dependent offset -> run -> LDS chains leave most of the
+// memory bandwidth free; both join back into s.
+hipError_t launch_fitness_kinds(const Meta &m, hipStream_t s, const Fork *fk)
 {
     hipError_t e;
-    if ((e = m.launch(K_FIT, s)) != hipSuccess) return e;
     if ((e = m.launch(K_BIN, s)) != hipSuccess) return e;
-    return m.launch(K_HIST, s);
+    hipStream_t scan = s;
+    if (fk && m.totals[K_HIST] > 0) {
+        if ((e = hipEventRecord(fk->fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(fk->side[0], fk->fork, 0)) != hipSuccess) return e;
+        scan = fk->side[0];
+    }
+    // k_hist first: its workgroups need 64 KB of LDS each and would otherwise find the CUs
+    // full of arc-scan waves
+    if ((e = m.launch(K_HIST, s)) != hipSuccess) return e;
+    if ((e = m.launch(K_FIT, scan)) != hipSuccess) return e;
+    if (scan != s) {
+        if ((e = hipEventRecord(fk->join[0], scan)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, fk->join[0], 0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-hipError_t launch_init_seq(const Meta &m, hipStream_t s)
+hipError_t launch_init_seq(const Meta &m, hipStream_t s, const Fork *fk)
 {
     hipError_t e;
     if ((e = m.launch(K_CLEAR, s)) != hipSuccess) return e;  // plain histograms start at zero
     if ((e = m.one(ONE_ZERO_ACC, s)) != hipSuccess) return e;
     if ((e = m.launch(K_INIT, s)) != hipSuccess) return e;
-    if ((e = launch_fitness_kinds(m, s)) != hipSuccess) return e;
+    if ((e = launch_fitness_kinds(m, s, fk)) != hipSuccess) return e;
     if ((e = m.launch(K_CLEAR, s)) != hipSuccess) return e;
     return m.one(ONE_INIT_STATE, s);
 }
@@ -285,7 +302,7 @@ hipError_t launch_generation(const Meta &m, hipStream_t s, const EventPair *ev, 
     if ((e = launch_mutation(m, s, fk)) != hipSuccess) return e;
     mark(1, true);
     mark(2, false);
-    if ((e = launch_fitness_kinds(m, s)) != hipSuccess) return e;
+    if ((e = launch_fitness_kinds(m, s, fk)) != hipSuccess) return e;
     mark(2, true);
     mark(3, false);
     if ((e = m.launch(K_CLEAR, s)) != hipSuccess) return e;
@@ -535,7 +552,7 @@ static int autotune(const hpmocd_graph *const *graphs, int32_t count, const hpmo
         Batch bt;
         int rc = bt.setup(graphs, count, probe.data(), ws, ws_bytes, t, true, s);
         if (rc) return rc;
-        HIP_TRY(launch_init_seq(bt.meta[0], s));
+        HIP_TRY(launch_init_seq(bt.meta[0], s, &bt.fork));
         HIP_TRY(hipEventRecord(a, s));
         rc = bt.generations(1, 2, s, false, nullptr, nullptr, nullptr, false);
         if (rc) return rc;
@@ -631,7 +648,7 @@ int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_par
     HIP_TRY(mi.one(ONE_ZERO_ACC, s));
     HIP_TRY(mi.launch(K_INIT, s));
     if (prof) HIP_TRY(hipEventRecord(e_fit0, s));
-    HIP_TRY(launch_fitness_kinds(mi, s));
+    HIP_TRY(launch_fitness_kinds(mi, s, &B.fork));
     if (prof) HIP_TRY(hipEventRecord(e_fit1, s));
     HIP_TRY(mi.launch(K_CLEAR, s));
     HIP_TRY(mi.one(ONE_INIT_STATE, s));
@@ -830,7 +847,7 @@ int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, v
         if (!a || !b) return HPMOCD_ERR_HIP;
         HIP_TRY(hipEventRecord(a, s));
     }
-    HIP_TRY(launch_fitness_kinds(m, s));
+    HIP_TRY(launch_fitness_kinds(m, s, nullptr));
     if (kernel_ms) HIP_TRY(hipEventRecord(b, s));
     HIP_TRY(launch_finalize(G->m2, n_ind, dA, dS, df1, df2, s));
     std::vector<unsigned long long> hA(n_ind), hS(n_ind);

@@ -106,8 +106,8 @@ struct Fork {
     ~Fork();
 };
 
-hipError_t launch_fitness_kinds(const Meta &m, hipStream_t s);
-hipError_t launch_init_seq(const Meta &m, hipStream_t s);
+hipError_t launch_fitness_kinds(const Meta &m, hipStream_t s, const Fork *fk);
+hipError_t launch_init_seq(const Meta &m, hipStream_t s, const Fork *fk);
 // fk == nullptr: every kernel on s, one after another
 hipError_t launch_generation(const Meta &m, hipStream_t s, const EventPair *ev, const Fork *fk);
 int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, void *user,

@@ -190,7 +190,7 @@ int hpmocd_server::step(std::vector<Request *> &admitted)
     if (!init_items.empty()) {
         int rc = m_init.upload(init_items, tables, stream);
         if (rc) return rc;
-        HIP_TRY(launch_init_seq(m_init, stream));
+        HIP_TRY(launch_init_seq(m_init, stream, &fork));
     }
     if (!gen_items.empty()) {
         int rc = m_gen.upload(gen_items, tables + tb, stream);
