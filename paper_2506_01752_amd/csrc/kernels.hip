@@ -899,6 +899,9 @@ __device__ __forceinline__ int ensemble_plurality(const int (&L)[ES], uint64_t s
     return out;
 }
 
+// ints of k_crossover's LDS tables (pos_id, gate, par_id), rounded up to 16 bytes
+__host__ __device__ inline int xo_table_ints(int pop, int es) { return ((2 + es) * pop + 3) & ~3; }
+
 template <int ES>
 __global__ __launch_bounds__(256) void k_crossover(Span sp)
 {
@@ -913,19 +916,32 @@ __global__ __launch_bounds__(256) void k_crossover(Span sp)
     GLB int32_t *__restrict__ C = glb(it.C);
     GLB int32_t *__restrict__ q_next = glb(it.q_next);
     const FastDiv divpop((uint32_t)c.pop);
-    extern __shared__ int xs[];  // [pop] pos_id, [pop] gate, [pop * ES] par_id
+    // LDS: [pop] pos_id, [pop] gate, [pop * ES] par_id, then (16-byte aligned) the block's
+    // rows of the committed pool and of the offspring plane, [nblock * ld] each
+    extern __shared__ __align__(16) int xs[];
     const int pop = c.pop, ld = c.ld;
     int *s_pos = xs, *s_gate = xs + pop, *s_par = xs + 2 * pop;
+    int *s_pool = xs + xo_table_ints(pop, ES), *s_q = s_pool + (size_t)nblock * ld;
     for (int t = threadIdx.x; t < pop; t += blockDim.x) {
         s_pos[t] = st.pos_id[t];
         s_gate[t] = st.gate[t];
     }
     for (int t = threadIdx.x; t < pop * ES; t += blockDim.x) s_par[t] = st.par_id[t];
-    __syncthreads();
     const uint32_t g = (uint32_t)*st.gen;
     const int64_t v0 = (int64_t)lb * nblock;
     const int nv = (int)min((int64_t)nblock, (int64_t)n - v0);
     const uint32_t items = (uint32_t)nv * (uint32_t)pop;
+    {   // consecutive nodes' rows are one contiguous span: 16-byte loads (ld is a multiple of 16)
+        const int4 *gp = (const int4 *)(pool_cur + (size_t)v0 * ld);
+        const int4 *gq = (const int4 *)(q_cur + (size_t)v0 * ld);
+        int4 *lp = (int4 *)s_pool, *lq = (int4 *)s_q;
+        const int n4 = nv * ld / 4;
+        for (int t = threadIdx.x; t < n4; t += blockDim.x) {
+            lp[t] = gp[t];
+            lq[t] = gq[t];
+        }
+    }
+    __syncthreads();
     // XO_ITEMS (node, offspring) items per thread at once: all their loads are issued
     // before any plurality is resolved
     constexpr int XO_ITEMS = 4;
@@ -944,8 +960,8 @@ __global__ __launch_bounds__(256) void k_crossover(Span sp)
             jj[t] = (int)(fq - q * (uint32_t)pop);
             vv[t] = (uint32_t)(v0 + q);
             row[t] = (size_t)vv[t] * ld;
-            const GLB int32_t *prow = pool_cur + row[t];
-            const GLB int32_t *qrow = q_cur + row[t] - pop;  // indexed by id >= pop
+            const int *prow = s_pool + (size_t)q * ld;
+            const int *qrow = s_q + (size_t)q * ld - pop;  // indexed by id >= pop
             const int id = s_pos[jj[t]];
             commit[t] = id < pop ? prow[id] : qrow[id];
             gk[t] = s_gate[jj[t]];
@@ -1567,7 +1583,8 @@ size_t kind_lds(Kind k, const Item &it)
                                                    (size_t)it.hp.nb * HB_CG + 4)
                              : 0;
     case K_HIST: return it.hp.enabled ? sizeof(uint32_t) * ((size_t)1 << it.hp.rbits) : 0;
-    case K_XO: return sizeof(int) * (size_t)it.c.pop * (size_t)(2 + it.c.es);
+    case K_XO:
+        return sizeof(int) * ((size_t)xo_table_ints(it.c.pop, it.c.es) + 2 * (size_t)it.xo_nb * it.c.ld);
     case K_MUTL:
         return sizeof(int) * (2 * (size_t)HPMOCD_MAX_POP_DEV + MUT_WAVES + 4 +
                               2 * (size_t)large_pmax(it));

@@ -124,7 +124,10 @@ void Pop::shape(const Tuning &t, int64_t batch_nodes)
     const int64_t npw = batch_nodes / std::max<int64_t>(1, t.fit_target_waves);
     fit_npw = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, npw));
     const int64_t nb = batch_nodes / std::max<int64_t>(1, t.xo_target_blocks);
-    xo_nb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(32, nb));
+    // the crossover stages its nodes' two rows in LDS beside its tables: 64 KB in all
+    const int64_t tables = 4 * ((((int64_t)2 + p.parents_per_child) * p.pop_size + 3) & ~3);
+    const int64_t lds_nodes = std::max<int64_t>(1, (65536 - tables) / (8 * (int64_t)L.ld));
+    xo_nb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(32, lds_nodes), nb));
 }
 
 Item Pop::item(int which) const
