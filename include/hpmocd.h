@@ -159,6 +159,29 @@ int hpmocd_run_batch(const hpmocd_graph *const *graphs, int32_t count,
                      const hpmocd_params *params, void *d_workspace, size_t ws_bytes,
                      void *stream, int flags, hpmocd_profile *profile, hpmocd_front **outs);
 
+/* Checkpoint / resume. A snapshot is the population of a run after environmental selection
+ * of generation g (g = 0: the initial population) in selection order, which is all a run
+ * carries from one generation to the next: the random draws are a function of (seed, g,
+ * individual, node) and need no saved state. Host memory owned by the library. */
+typedef struct {
+    int32_t g;            /* generations completed */
+    int32_t pop_size, n_nodes;
+    int32_t *labels;      /* pop_size x n_nodes, row-major, in selection order */
+    int64_t *A, *S;       /* objectives' integer numerators of each member */
+} hpmocd_snapshot;
+
+/* Runs initialisation and generations 1..stop_gen (0 <= stop_gen <= p->generations) and
+ * returns the snapshot in *out instead of a front. Workspace as for hpmocd_run. */
+int hpmocd_run_to(const hpmocd_graph *g, const hpmocd_params *p, int32_t stop_gen,
+                  void *d_workspace, size_t ws_bytes, void *stream, hpmocd_snapshot **out);
+/* Continues a run from a snapshot taken with the same graph and parameters: generations
+ * snap->g + 1 .. p->generations, then the front. The result equals the uninterrupted
+ * hpmocd_run bit for bit. The snapshot is validated (sizes, g <= T, labels in [0, n)) before
+ * any device work. */
+int hpmocd_resume(const hpmocd_graph *g, const hpmocd_params *p, const hpmocd_snapshot *snap,
+                  void *d_workspace, size_t ws_bytes, void *stream, hpmocd_front **out);
+void hpmocd_snapshot_free(hpmocd_snapshot *s);
+
 /* Fitness alone (eq. objectives) for n_ind partitions given as device memory, row-major
  * n_ind x n int32 labels in [0, n) (values outside are an error the kernel cannot report:
  * the caller guarantees the range). Writes A, S, f1, f2 (host arrays of n_ind). */

@@ -44,6 +44,7 @@ EXPORTS = [
     "hpmocd_server_arena_overhead", "hpmocd_server_create", "hpmocd_server_submit",
     "hpmocd_server_poll", "hpmocd_server_wait", "hpmocd_server_cancel",
     "hpmocd_server_stats_get", "hpmocd_server_destroy",
+    "hpmocd_run_to", "hpmocd_resume", "hpmocd_snapshot_free",
 ]
 
 
@@ -86,6 +87,12 @@ class Profile(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class _Snapshot(C.Structure):
+    _fields_ = [("g", C.c_int32), ("pop_size", C.c_int32), ("n_nodes", C.c_int32),
+                ("labels", C.POINTER(C.c_int32)), ("A", C.POINTER(C.c_int64)),
+                ("S", C.POINTER(C.c_int64))]
 
 
 class ServerConfig(C.Structure):
@@ -155,11 +162,18 @@ def lib():
         L.hpmocd_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
         L.hpmocd_server_destroy.argtypes = [vp]
         L.hpmocd_server_destroy.restype = None
+        L.hpmocd_run_to.argtypes = [vp, C.POINTER(Params), C.c_int32, vp, C.c_size_t, vp,
+                                    C.POINTER(C.POINTER(_Snapshot))]
+        L.hpmocd_resume.argtypes = [vp, C.POINTER(Params), C.POINTER(_Snapshot), vp, C.c_size_t,
+                                    vp, C.POINTER(C.POINTER(_Front))]
+        L.hpmocd_snapshot_free.argtypes = [C.POINTER(_Snapshot)]
+        L.hpmocd_snapshot_free.restype = None
         L.hpmocd_strerror.argtypes = [C.c_int]
         L.hpmocd_strerror.restype = C.c_char_p
         for name in EXPORTS:
             if name not in ("hpmocd_graph_destroy", "hpmocd_front_free", "hpmocd_strerror",
-                            "hpmocd_server_destroy", "hpmocd_server_arena_overhead"):
+                            "hpmocd_server_destroy", "hpmocd_server_arena_overhead",
+                            "hpmocd_snapshot_free"):
                 getattr(L, name).restype = C.c_int
         L.hpmocd_server_arena_overhead.restype = C.c_size_t
         _lib = L
@@ -311,6 +325,57 @@ def run(graph: Graph, params: Params | None = None, *, stream=None, workspace=No
     _check(st, "hpmocd_run_ex")
     front = _front_from(out)
     return (front, prof.as_dict()) if profile else front
+
+
+@dataclass
+class Snapshot:
+    g: int               # generations completed
+    labels: np.ndarray   # (pop, n) int32, selection order
+    A: np.ndarray
+    S: np.ndarray
+
+
+def run_to(graph: Graph, params: Params | None = None, *, stop_gen: int, stream=None,
+           workspace=None, **kw) -> Snapshot:
+    """hpmocd_run_to: the population after generation stop_gen (checkpoint)."""
+    import torch
+    if params is None:
+        params = make_params(**kw)
+    nbytes = workspace_size(graph, params)
+    ws = workspace if workspace is not None else torch.empty(nbytes, dtype=torch.uint8,
+                                                             device="cuda")
+    out = C.POINTER(_Snapshot)()
+    _check(lib().hpmocd_run_to(graph.handle, C.byref(params), stop_gen,
+                               C.c_void_p(ws.data_ptr()), nbytes, _stream_handle(stream),
+                               C.byref(out)), "hpmocd_run_to")
+    sn = out.contents
+    res = Snapshot(sn.g, np.ctypeslib.as_array(sn.labels, shape=(sn.pop_size, sn.n_nodes)).copy(),
+                   np.ctypeslib.as_array(sn.A, shape=(sn.pop_size,)).copy(),
+                   np.ctypeslib.as_array(sn.S, shape=(sn.pop_size,)).copy())
+    lib().hpmocd_snapshot_free(out)
+    return res
+
+
+def resume(graph: Graph, snapshot: Snapshot, params: Params | None = None, *, stream=None,
+           workspace=None, **kw) -> Front:
+    """hpmocd_resume: continue a run from a snapshot to params.generations."""
+    import torch
+    if params is None:
+        params = make_params(**kw)
+    labels = np.ascontiguousarray(snapshot.labels, dtype=np.int32)
+    A = np.ascontiguousarray(snapshot.A, dtype=np.int64)
+    S = np.ascontiguousarray(snapshot.S, dtype=np.int64)
+    sn = _Snapshot(snapshot.g, labels.shape[0], labels.shape[1],
+                   labels.ctypes.data_as(C.POINTER(C.c_int32)),
+                   A.ctypes.data_as(C.POINTER(C.c_int64)), S.ctypes.data_as(C.POINTER(C.c_int64)))
+    nbytes = workspace_size(graph, params)
+    ws = workspace if workspace is not None else torch.empty(nbytes, dtype=torch.uint8,
+                                                             device="cuda")
+    out = C.POINTER(_Front)()
+    _check(lib().hpmocd_resume(graph.handle, C.byref(params), C.byref(sn),
+                               C.c_void_p(ws.data_ptr()), nbytes, _stream_handle(stream),
+                               C.byref(out)), "hpmocd_resume")
+    return _front_from(out)
 
 
 def run_batch(graphs, params, *, stream=None, workspace=None, flags=0, profile=False):

@@ -775,6 +775,107 @@ int hpmocd_run_batch(const hpmocd_graph *const *graphs, int32_t count,
 }
 
 // ---------------------------------------------------------------------------------------
+// checkpoint / resume
+// ---------------------------------------------------------------------------------------
+void hpmocd_snapshot_free(hpmocd_snapshot *sn)
+{
+    if (!sn) return;
+    std::free(sn->labels);
+    std::free(sn->A);
+    std::free(sn->S);
+    std::free(sn);
+}
+
+int hpmocd_run_to(const hpmocd_graph *G, const hpmocd_params *p, int32_t stop_gen, void *ws,
+                  size_t ws_bytes, void *stream, hpmocd_snapshot **out)
+{
+    if (!G || !p || !out || !ws) return HPMOCD_ERR_ARG;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (stop_gen < 0 || stop_gen > p->generations) return HPMOCD_ERR_ARG;
+    if ((rc = check_device(G))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Batch B;
+    if ((rc = B.setup(&G, 1, p, ws, ws_bytes, Tuning{}, false, s))) return rc;
+    HIP_TRY(launch_init_seq(B.meta[0], s, &B.fork));
+    if ((rc = B.generations(1, stop_gen, s, s != nullptr, nullptr, nullptr, nullptr, false)))
+        return rc;
+    // members in selection order, gathered into row-major rows (C is free here)
+    const Pop &P = B.pops[0];
+    const int32_t n = G->n, pop = p->pop_size;
+    HIP_TRY(launch_extract(n, P.c.ld, pop, P.L.pool[P.cur], P.L.q[P.cur], P.L.st.ps_id, pop,
+                           P.L.C, s));
+    hpmocd_snapshot *sn = (hpmocd_snapshot *)std::calloc(1, sizeof(hpmocd_snapshot));
+    if (!sn) return HPMOCD_ERR_NOMEM;
+    sn->g = stop_gen;
+    sn->pop_size = pop;
+    sn->n_nodes = n;
+    sn->labels = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)pop * n);
+    sn->A = (int64_t *)std::malloc(sizeof(int64_t) * pop);
+    sn->S = (int64_t *)std::malloc(sizeof(int64_t) * pop);
+    if (!sn->labels || !sn->A || !sn->S) {
+        hpmocd_snapshot_free(sn);
+        return HPMOCD_ERR_NOMEM;
+    }
+    const hipMemcpyKind d2h = hipMemcpyDeviceToHost;
+    bool ok = hipMemcpyAsync(sn->labels, P.L.C, sizeof(int32_t) * (size_t)pop * n, d2h, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(sn->A, P.L.st.ps_A, sizeof(int64_t) * pop, d2h, s) == hipSuccess;
+    ok = ok && hipMemcpyAsync(sn->S, P.L.st.ps_S, sizeof(int64_t) * pop, d2h, s) == hipSuccess;
+    ok = ok && hipStreamSynchronize(s) == hipSuccess;
+    if (!ok) {
+        hpmocd_snapshot_free(sn);
+        return HPMOCD_ERR_HIP;
+    }
+    *out = sn;
+    return HPMOCD_OK;
+}
+
+int hpmocd_resume(const hpmocd_graph *G, const hpmocd_params *p, const hpmocd_snapshot *sn,
+                  void *ws, size_t ws_bytes, void *stream, hpmocd_front **out)
+{
+    if (!G || !p || !sn || !out || !ws || !sn->labels || !sn->A || !sn->S) return HPMOCD_ERR_ARG;
+    int rc = check_params(p);
+    if (rc) return rc;
+    const int32_t n = G->n, pop = p->pop_size, T = p->generations;
+    if (sn->n_nodes != n || sn->pop_size != pop || sn->g < 0 || sn->g > T) return HPMOCD_ERR_ARG;
+    for (size_t i = 0; i < (size_t)pop * n; ++i)
+        if (sn->labels[i] < 0 || sn->labels[i] >= n) return HPMOCD_ERR_RANGE;
+    const int64_t m2 = G->m2;
+    std::vector<int32_t> ids(pop);
+    std::vector<double> f1(pop), f2(pop);
+    for (int32_t i = 0; i < pop; ++i) {
+        if (sn->A[i] < 0 || sn->A[i] > m2 || sn->S[i] < 0 || sn->S[i] > m2 * m2)
+            return HPMOCD_ERR_RANGE;
+        ids[i] = i;  // member i lives in column i of the committed pool
+        f1[i] = (double)(m2 - sn->A[i]) / (double)m2;   // eq. objectives, as the kernels do
+        f2[i] = (double)sn->S[i] / (double)(m2 * m2);
+    }
+    if ((rc = check_device(G))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Batch B;
+    if ((rc = B.setup(&G, 1, p, ws, ws_bytes, Tuning{}, false, s))) return rc;
+    Pop &P = B.pops[0];
+    P.cur = 0;
+    const DevState &st = P.L.st;
+    const int32_t gen = sn->g + 1;  // the device generation counter after selection of g
+    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+    HIP_TRY(hipMemcpyAsync(P.L.C, sn->labels, sizeof(int32_t) * (size_t)pop * n, h2d, s));
+    HIP_TRY(launch_transpose_in(P.L.C, n, pop, P.c.ld, P.L.pool[0], s));
+    HIP_TRY(hipMemcpyAsync(st.ps_id, ids.data(), sizeof(int32_t) * pop, h2d, s));
+    HIP_TRY(hipMemcpyAsync(st.ps_A, sn->A, sizeof(int64_t) * pop, h2d, s));
+    HIP_TRY(hipMemcpyAsync(st.ps_S, sn->S, sizeof(int64_t) * pop, h2d, s));
+    HIP_TRY(hipMemcpyAsync(st.ps_f1, f1.data(), sizeof(double) * pop, h2d, s));
+    HIP_TRY(hipMemcpyAsync(st.ps_f2, f2.data(), sizeof(double) * pop, h2d, s));
+    HIP_TRY(hipMemcpyAsync(st.gen, &gen, sizeof(int32_t), h2d, s));
+    HIP_TRY(B.meta[1].launch(K_CLEAR, s));  // the plain histogram plane starts at zero
+    if ((rc = B.generations(sn->g + 1, T, s, s != nullptr, nullptr, nullptr, nullptr, false)))
+        return rc;
+    HIP_TRY(B.meta[1 + P.cur].one(ONE_FINAL, s));
+    rc = extract_front(P, s, out);  // synchronises s: the host arrays above outlive the copies
+    return rc;
+}
+
+// ---------------------------------------------------------------------------------------
 // fitness alone (eval)
 // ---------------------------------------------------------------------------------------
 int hpmocd_eval_workspace_size(const hpmocd_graph *g, int32_t n_ind, size_t *bytes)
