@@ -222,9 +222,10 @@ __global__ __launch_bounds__(256) void k_init(Span sp)
 // undirected edge once, as the upper arc (v,u) with u > v, reads the node-major row of u (a
 // contiguous 8-byte-per-lane load), compares with v's row and counts per lane; the count is
 // doubled at the end. v, its arc range and the neighbour ids are wave-uniform (scalar loads).
-// Community degree sums: D[label][col] += deg(v) by device-scope atomics whose returned
-// old value gives S exactly, since sum over the additions of (old + d)^2 - old^2 telescopes
-// to sum_c D_c^2 whatever order the atomics take.
+// Community degree sums, small problems only (larger ones use the binned histogram below):
+// D[label][col] += deg(v) by device-scope atomics whose returned old value gives S exactly,
+// since sum over the additions of (old + d)^2 - old^2 telescopes to sum_c D_c^2 whatever
+// order the atomics take.
 // ---------------------------------------------------------------------------------------
 constexpr int FIT_ARCS = 16;   // arcs in flight per wave in the scan phase
 constexpr int FIT_NODES = 8;   // nodes per batch in the histogram phase
@@ -1229,8 +1230,10 @@ __device__ __forceinline__ int wave_plurality(const GLB int32_t *__restrict__ C,
     return res;
 }
 
-// Degree class (64(E/2), 64E]: a wave per node draws the MUT words of all offspring, queues
-// the mutating ones in LDS and resolves them one at a time with the wave sort.
+// Degree class (64(E/2), 64E]: a wave takes one node and a slice of its offspring, draws
+// their MUT words, queues the mutating ones in LDS and resolves them one at a time with the
+// wave sort.
+//
 // Waves per node in the wave classes: a node's offspring are split into this many slices so
 // that one wave resolves about `per` mutations (a node has pop * M_P of them on average). One
 // wave per node left the few high-degree nodes' waves resolving ten or more wave-wide sorts
