@@ -219,3 +219,28 @@ def test_binned_histogram_small_population_1m(hp, stream, pop):
                                     seed=21)
     assert_states_equal(gs, os_)
     assert_front_equal(got, ref)
+
+
+def test_random_sweep_against_oracle(hp, stream):
+    """Seeded random graphs (random, two-level planted, stars with isolated nodes) and random
+    parameters; every front bit-exact against the oracle."""
+    rng = np.random.default_rng(2024)
+    for case in range(40):
+        kind = case % 3
+        if kind == 0:
+            g = synth.gnp(int(rng.integers(2, 300)), float(rng.uniform(0.01, 0.3)), case)
+        elif kind == 1:
+            g = synth.planted_partition(int(rng.integers(50, 600)), float(rng.uniform(3, 12)), 40,
+                                        float(rng.uniform(0.05, 0.6)), 5, 60, seed=case)
+        else:
+            g = synth.with_isolated(synth.star(int(rng.integers(3, 80))), int(rng.integers(0, 9)))
+        if g.m == 0:
+            continue
+        kw = dict(pop_size=int(rng.integers(1, 70)), generations=int(rng.integers(0, 7)),
+                  crossover_p=float(rng.choice([0.0, 0.5, 0.9, 1.0])),
+                  mutation_p=float(rng.choice([0.0, 0.05, 0.3, 1.0])),
+                  parents_per_child=int(rng.integers(1, 9)), seed=int(rng.integers(0, 2**62)))
+        say(f"case {case}: n={g.n} m={g.m} {kw}")
+        got = hp.run(hp.Graph(g.row_ptr, g.col), stream=stream, **kw)
+        ref = oracle.run(g.row_ptr, g.col, threads=4, **kw)
+        assert_front_equal(got, ref)
