@@ -43,9 +43,10 @@ def population_floor_bytes(n: int, m2: int, pop: int) -> int:
     return 4 * (n + 1) + 4 * m2 + 4 * n * pop
 
 
-def measured_traffic(workload: str, pop: int):
-    """HBM bytes of one fitness step from the committed rocprofv3 counter summary, or None
-    when there is none for this workload or the kernels changed since it was taken."""
+def measured_counter(workload: str, pop: int, key: str = "fitness_step_traffic_bytes"):
+    """A figure of the committed rocprofv3 counter summary (HBM bytes of one fitness step, or
+    the fitness kernels' L2 hit rate), or None when there is none for this workload or the
+    kernels changed since it was taken."""
     import hashlib
     import re
     if workload != "planted_partition_1M" or pop != 100:
@@ -55,11 +56,35 @@ def measured_traffic(workload: str, pop: int):
         return None
     text = open(path).read()
     m_sha = re.search(r"kernels.hip sha256 prefix when measured: ([0-9a-f]+)", text)
-    m_val = re.search(r"fitness_step_traffic_bytes: (\d+)", text)
+    m_val = re.search(re.escape(key) + r": ([0-9.]+)", text)
     src = open(os.path.join(ROOT, "paper_2506_01752_amd", "csrc", "kernels.hip"), "rb").read()
     if not m_sha or not m_val or hashlib.sha256(src).hexdigest()[:16] != m_sha.group(1):
         return None
-    return int(m_val.group(1))
+    v = m_val.group(1)
+    return float(v) if "." in v else int(v)
+
+
+def measured_traffic(workload: str, pop: int):
+    return measured_counter(workload, pop)
+
+
+def copy_ceiling_gbps(mib: int = 1024, reps: int = 5) -> float:
+    """Achievable HBM bandwidth on this device: a plain device-to-device copy of mib MiB
+    (bytes read + bytes written per second, best of reps)."""
+    import torch
+    a = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        best = max(best, 2 * a.numel() / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    del a, b
+    return best
 
 
 def cpu_baseline(g, seed: int, target_s: float = 15.0):
@@ -413,6 +438,7 @@ def main():
     eval_ms = (fit_ms + sweep_ms) / launches      # one whole-population evaluation
     bytes_launch = pop * per_individual_bytes(g.n, 2 * g.m)
     achieved = bytes_launch / (eval_ms / 1e3) / 1e9
+    copy_gbps = copy_ceiling_gbps()
     out = {
         "metric": METRIC,
         "value": value,
@@ -442,7 +468,9 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": measured_traffic(args.workload, pop),
-                     "bytes_per_launch": bytes_launch, "ms_per_launch": eval_ms},
+                     "bytes_per_launch": bytes_launch, "ms_per_launch": eval_ms,
+                     "l2_hit_rate": measured_counter(args.workload, pop, "fitness_l2_hit_rate"),
+                     "copy_ceiling_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps},
     }
     if args.graph_mode and T >= 2:
         torch.cuda.synchronize()
