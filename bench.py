@@ -112,6 +112,31 @@ def cpu_baseline(g, seed: int, target_s: float = 15.0):
                       f"({reps * k} individual evaluations), serial C oracle, {dt:.2f} s"}
 
 
+def cpu_generation(g, kw, threads: int):
+    """Context beside cpu_baseline: one whole oracle generation (tournament, crossover,
+    mutation, evaluation, selection) with OpenMP over individuals on the host's cores, as the
+    difference of a one-generation run and a zero-generation run."""
+    import oracle
+    oracle.build()
+
+    def timed(T):
+        t0 = time.perf_counter()
+        oracle.run(g.row_ptr, g.col, **dict(kw, generations=T), threads=threads)
+        return time.perf_counter() - t0
+    t0 = timed(0)
+    t1 = timed(1)
+    model = "?"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"seconds_per_generation": max(t1 - t0, 1e-9), "threads": threads,
+            "cpu_model": model, "kind": "oracle"}
+
+
 def bench_batched(args):
     """Batched form: many independent runs (each graph with its own pop-64 population) in one
     batched call vs the same runs one after another; results must be identical."""
@@ -484,6 +509,8 @@ def main():
                              "gens_per_s": T * args.steps / (sum(loops) / 1e3)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, kw["seed"])
+        # host cores: the GPU machine grants 16 to a job whatever the machine shows
+        out["cpu_oracle_generation"] = cpu_generation(g, kw, min(16, os.cpu_count() or 1))
     print(json.dumps(out), flush=True)
 
 
