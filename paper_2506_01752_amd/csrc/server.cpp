@@ -98,14 +98,26 @@ struct Request {
 
 using namespace hpm;
 
+// One launched step that has not been completed yet. Its host-side table copies, the host
+// graphs of the requests it admitted, the fronts of the requests it finished and the memory
+// of requests cancelled while it ran are settled only once its event has fired.
+struct Flight {
+    bool valid = false;
+    hipEvent_t done = nullptr;
+    Meta m_init, m_gen, m_final;
+    std::vector<Request *> admitted, finals, released;
+};
+
 struct hpmocd_server {
     hpmocd_server_config cfg{};
     char *arena = nullptr;        // caller's device memory
-    size_t table_bytes = 0;       // three item tables at the start of the arena
+    size_t table_bytes = 0;       // two sets of three item tables at the start of the arena
     hipStream_t stream = nullptr;
+    hipStream_t copy_stream = nullptr;  // front extraction beside the next step
     int device = 0;
     Tuning tuning;
     Fork fork;  // side streams of the mutation classes
+    Flight flight[2];
     Clock::time_point epoch;
 
     std::mutex mu;
@@ -115,7 +127,7 @@ struct hpmocd_server {
     int64_t next_ticket = 1;
     std::map<int64_t, std::unique_ptr<Request>> reqs;
     std::deque<Request *> queue;
-    std::vector<Request *> active;  // touched by the scheduler thread only
+    std::vector<Request *> active;  // resident and still running; scheduler thread only
     Arena alloc;
     size_t used = 0;
     hpmocd_server_stats stats{};
@@ -123,13 +135,22 @@ struct hpmocd_server {
 
     double now() const { return std::chrono::duration<double>(Clock::now() - epoch).count(); }
     void run();
-    int step(std::vector<Request *> &admitted);
-    void finish(Request *r, int status);  // caller holds mu
+    int launch(Flight &f, int set, std::vector<Request *> &admitted);
+    int complete(Flight &f);
+    int run_fifo(Request *r);
+    void release(Request *r, int status);  // caller holds mu
+    void finish(Request *r, int status);   // caller holds mu
+    ~hpmocd_server()
+    {
+        for (Flight &f : flight)
+            if (f.done) (void)hipEventDestroy(f.done);
+        if (copy_stream) (void)hipStreamDestroy(copy_stream);
+    }
 };
 
 size_t hpmocd_server_arena_overhead(int32_t max_active)
 {
-    return 3 * align_up(meta_bytes(std::max(1, max_active)));
+    return 6 * align_up(meta_bytes(std::max(1, max_active)));
 }
 
 void hpmocd_server::finish(Request *r, int st)
@@ -143,29 +164,41 @@ void hpmocd_server::finish(Request *r, int st)
         ++stats.completed;
 }
 
-// One scheduler step over `active` (admitted requests included, flagged fresh). Runs without
-// the lock; the stream is idle on entry and on return.
-int hpmocd_server::step(std::vector<Request *> &admitted)
+void hpmocd_server::release(Request *r, int st)
 {
-    if (cfg.flags & HPMOCD_SERVER_FIFO) {  // baseline: the one resident request as a plain run
-        Request *r = active.front();
-        int rc = place_graph(r->hg, arena + r->off, stream, &r->graph);
-        if (rc) return rc;
-        const hpmocd_graph *gp = &r->graph;
-        rc = run_batch(&gp, 1, &r->p, arena + r->off + r->graph_bytes, r->bytes - r->graph_bytes,
-                       stream, 0, nullptr, nullptr, nullptr, &r->front);
-        if (rc) return rc;  // run_batch returns with the stream drained
-        r->hg = HostGraph();
-        r->steps = 1;
-        r->max_mix = 1;
-        std::lock_guard<std::mutex> lk(mu);
-        alloc.release(r->off, r->bytes);
-        used -= r->bytes;
-        finish(r, HPMOCD_OK);
-        active.clear();
-        cv_done.notify_all();
-        return HPMOCD_OK;
-    }
+    alloc.release(r->off, r->bytes);
+    used -= r->bytes;
+    finish(r, st);
+}
+
+static void drop_host_graph(Request *r) { r->hg = HostGraph(); }
+
+// FIFO baseline: the one resident request as a plain hipGraph-replayed run (synchronous).
+int hpmocd_server::run_fifo(Request *r)
+{
+    int rc = place_graph(r->hg, arena + r->off, stream, &r->graph);
+    if (rc) return rc;
+    const hpmocd_graph *gp = &r->graph;
+    rc = run_batch(&gp, 1, &r->p, arena + r->off + r->graph_bytes, r->bytes - r->graph_bytes,
+                   stream, 0, nullptr, nullptr, nullptr, &r->front);
+    if (rc) return rc;  // run_batch returns with the stream drained
+    drop_host_graph(r);
+    r->steps = 1;
+    r->max_mix = 1;
+    std::lock_guard<std::mutex> lk(mu);
+    release(r, HPMOCD_OK);
+    active.clear();
+    cv_done.notify_all();
+    return HPMOCD_OK;
+}
+
+// Launches one step over `active` (admitted requests included) into table set `set`, without
+// waiting: copies the new graphs, initialises the new populations, advances every running
+// request one generation and ranks those that reach T (which leave `active`).
+int hpmocd_server::launch(Flight &f, int set, std::vector<Request *> &admitted)
+{
+    f.admitted = admitted;
+    f.finals.clear();
     for (Request *r : admitted) {
         int rc = place_graph(r->hg, arena + r->off, stream, &r->graph);
         if (rc) return rc;
@@ -175,7 +208,7 @@ int hpmocd_server::step(std::vector<Request *> &admitted)
     int64_t nodes = 0;
     for (Request *r : active) nodes += r->graph.n;
     std::vector<Item> init_items, gen_items, final_items;
-    std::vector<Request *> gen_reqs, final_reqs;
+    std::vector<Request *> gen_reqs;
     for (Request *r : active) {
         r->pop.shape(tuning, nodes);
         if (r->fresh) init_items.push_back(r->pop.item(ITEM_INIT));
@@ -184,18 +217,17 @@ int hpmocd_server::step(std::vector<Request *> &admitted)
             gen_reqs.push_back(r);
         }
     }
-    Meta m_init, m_gen, m_final;
-    char *tables = arena;
     const size_t tb = align_up(meta_bytes(cfg.max_active));
+    char *tables = arena + (size_t)set * 3 * tb;
     if (!init_items.empty()) {
-        int rc = m_init.upload(init_items, tables, stream);
+        int rc = f.m_init.upload(init_items, tables, stream);
         if (rc) return rc;
-        HIP_TRY(launch_init_seq(m_init, stream, &fork));
+        HIP_TRY(launch_init_seq(f.m_init, stream, &fork));
     }
     if (!gen_items.empty()) {
-        int rc = m_gen.upload(gen_items, tables + tb, stream);
+        int rc = f.m_gen.upload(gen_items, tables + tb, stream);
         if (rc) return rc;
-        HIP_TRY(launch_generation(m_gen, stream, nullptr, &fork));
+        HIP_TRY(launch_generation(f.m_gen, stream, nullptr, &fork));
         for (Request *r : gen_reqs) {
             r->pop.cur = 1 - r->pop.cur;
             ++r->gens_done;
@@ -207,35 +239,41 @@ int hpmocd_server::step(std::vector<Request *> &admitted)
         r->max_mix = std::max<int32_t>(r->max_mix, (int32_t)active.size());
         if (r->gens_done == r->p.generations) {
             final_items.push_back(r->pop.item(ITEM_PARITY0));
-            final_reqs.push_back(r);
+            f.finals.push_back(r);
         }
     }
     if (!final_items.empty()) {
-        int rc = m_final.upload(final_items, tables + 2 * tb, stream);
+        int rc = f.m_final.upload(final_items, tables + 2 * tb, stream);
         if (rc) return rc;
-        HIP_TRY(m_final.one(ONE_FINAL, stream));
+        HIP_TRY(f.m_final.one(ONE_FINAL, stream));
+        active.erase(std::remove_if(active.begin(), active.end(),
+                                    [](Request *r) { return r->gens_done == r->p.generations; }),
+                     active.end());
     }
-    HIP_TRY(hipStreamSynchronize(stream));
-    for (Request *r : admitted) {  // graphs are on the device now
-        r->hg.col.clear();
-        r->hg.col.shrink_to_fit();
-        r->hg.rp.clear();
-        r->hg.rp.shrink_to_fit();
-    }
-    for (Request *r : final_reqs) {
-        int rc = extract_front(r->pop, stream, &r->front);
+    HIP_TRY(hipEventRecord(f.done, stream));
+    f.valid = true;
+    return HPMOCD_OK;
+}
+
+// Waits for a launched step, then settles it: host graphs of its admissions, fronts of its
+// finished requests (extracted on the copy stream, beside the step launched after it),
+// memory of its finished and cancelled requests.
+int hpmocd_server::complete(Flight &f)
+{
+    HIP_TRY(hipEventSynchronize(f.done));
+    for (Request *r : f.admitted) drop_host_graph(r);
+    for (Request *r : f.finals) {
+        int rc = extract_front(r->pop, copy_stream, &r->front);
         if (rc) return rc;
     }
     std::lock_guard<std::mutex> lk(mu);
-    for (Request *r : final_reqs) {
-        alloc.release(r->off, r->bytes);
-        used -= r->bytes;
-        finish(r, HPMOCD_OK);
-    }
-    active.erase(std::remove_if(active.begin(), active.end(),
-                                [](Request *r) { return r->state == HPMOCD_REQ_DONE; }),
-                 active.end());
-    if (!final_reqs.empty()) cv_done.notify_all();
+    for (Request *r : f.finals) release(r, HPMOCD_OK);
+    for (Request *r : f.released) release(r, HPMOCD_ERR_CANCELLED);
+    if (!f.finals.empty() || !f.released.empty()) cv_done.notify_all();
+    f.admitted.clear();
+    f.finals.clear();
+    f.released.clear();
+    f.valid = false;
     return HPMOCD_OK;
 }
 
@@ -245,25 +283,31 @@ void hpmocd_server::run()
         std::lock_guard<std::mutex> lk(mu);
         broken = HPMOCD_ERR_HIP;
     }
+    const bool fifo = (cfg.flags & HPMOCD_SERVER_FIFO) != 0;
+    int cur = 0;  // flight[cur] takes the next launch; flight[cur ^ 1] is the one in flight
     for (;;) {
         std::vector<Request *> admitted;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv_work.wait(lk, [&] { return stop || !queue.empty() || !active.empty(); });
+            cv_work.wait(lk, [&] {
+                return stop || !queue.empty() || !active.empty() || flight[cur ^ 1].valid;
+            });
             if (stop || broken) break;
-            // resident requests cancelled since the last step (the stream is idle)
+            // resident requests cancelled since the last launch: the step in flight may still
+            // use their memory, so it is released when that step completes
             for (Request *r : active)
                 if (r->cancel) {
-                    alloc.release(r->off, r->bytes);
-                    used -= r->bytes;
-                    finish(r, HPMOCD_ERR_CANCELLED);
+                    if (flight[cur ^ 1].valid)
+                        flight[cur ^ 1].released.push_back(r);
+                    else
+                        release(r, HPMOCD_ERR_CANCELLED);
                 }
             active.erase(std::remove_if(active.begin(), active.end(),
-                                        [](Request *r) { return r->state == HPMOCD_REQ_DONE; }),
+                                        [](Request *r) { return r->cancel; }),
                          active.end());
             cv_done.notify_all();
             while (!queue.empty() && (int32_t)active.size() < cfg.max_active &&
-                   !((cfg.flags & HPMOCD_SERVER_FIFO) && !active.empty())) {
+                   !(fifo && !active.empty())) {
                 Request *r = queue.front();
                 if (used + r->bytes > cfg.hbm_budget) break;  // arrival order: no overtaking
                 size_t off = 0;
@@ -279,30 +323,43 @@ void hpmocd_server::run()
             }
             stats.peak_active = std::max<int32_t>(stats.peak_active, (int32_t)active.size());
             stats.peak_bytes = std::max<int64_t>(stats.peak_bytes, (int64_t)used);
-            if (active.empty()) continue;
         }
         const double t0 = now();
-        int rc = step(admitted);
+        int rc = HPMOCD_OK;
+        bool launched = false;
+        if (!active.empty()) {
+            rc = fifo ? run_fifo(active.front()) : launch(flight[cur], cur, admitted);
+            launched = true;
+        }
+        if (!rc && flight[cur ^ 1].valid) rc = complete(flight[cur ^ 1]);
         std::lock_guard<std::mutex> lk(mu);
         stats.busy_s += now() - t0;
-        ++stats.steps;
-        if (rc) {  // a device failure ends the service: fail everything resident
+        if (launched) ++stats.steps;
+        if (rc) {
             broken = rc;
-            for (Request *r : active) {
-                used -= r->bytes;
-                finish(r, rc);
-            }
-            active.clear();
-            cv_done.notify_all();
             break;
         }
+        cur ^= 1;
     }
-    // shutdown (or failure): nothing queued will run
-    std::lock_guard<std::mutex> lk(mu);
+    // shutdown or failure: settle what was launched, then nothing queued will run
     (void)hipStreamSynchronize(stream);
-    for (Request *r : active) finish(r, broken ? broken : HPMOCD_ERR_CANCELLED);
+    (void)hipStreamSynchronize(copy_stream);
+    std::lock_guard<std::mutex> lk(mu);
+    const int fail = broken ? broken : HPMOCD_ERR_CANCELLED;
+    for (Flight &f : flight) {
+        for (Request *r : f.finals)
+            if (r->state != HPMOCD_REQ_DONE) release(r, fail);
+        for (Request *r : f.released)
+            if (r->state != HPMOCD_REQ_DONE) release(r, fail);
+        f.admitted.clear();
+        f.finals.clear();
+        f.released.clear();
+        f.valid = false;
+    }
+    for (Request *r : active)
+        if (r->state != HPMOCD_REQ_DONE) release(r, fail);
     active.clear();
-    for (Request *r : queue) finish(r, broken ? broken : HPMOCD_ERR_CANCELLED);
+    for (Request *r : queue) finish(r, fail);
     queue.clear();
     cv_done.notify_all();
 }
@@ -328,7 +385,11 @@ int hpmocd_server_create(const hpmocd_server_config *cfg, void *d_arena, size_t 
     s->table_bytes = over;
     s->stream = (hipStream_t)stream;
     s->epoch = Clock::now();
-    if (hipGetDevice(&s->device) != hipSuccess || s->fork.init() != HPMOCD_OK) {
+    bool ok = hipGetDevice(&s->device) == hipSuccess && s->fork.init() == HPMOCD_OK;
+    ok = ok && hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) == hipSuccess;
+    for (Flight &f : s->flight)
+        ok = ok && hipEventCreateWithFlags(&f.done, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
         delete s;
         return HPMOCD_ERR_HIP;
     }
