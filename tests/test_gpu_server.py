@@ -191,3 +191,28 @@ def test_server_budget_rejection_and_timeout(hp):
         srv.wait(t, timeout=120)
     assert e.value.status == hp.ERR_CANCELLED
     srv.close()
+
+
+def test_server_many_small_requests_wide_tables(hp):
+    """300 tiny requests with up to 512 resident (item tables of hundreds of entries, requests
+    finishing in almost every step); each front equals its run alone."""
+    import torch
+    rng = np.random.default_rng(12)
+    reqs = []
+    for i in range(300):
+        g = synth.gnp(int(rng.integers(5, 60)), 0.15, 1000 + i)
+        if g.m == 0:
+            continue
+        reqs.append((g, dict(pop_size=int(rng.integers(1, 40)), generations=int(rng.integers(0, 9)),
+                             seed=int(rng.integers(0, 2**32)))))
+    srv = hp.Server(hbm_budget=1 << 30, max_active=512)
+    tickets = [srv.submit(g.row_ptr, g.col, **kw)[0] for g, kw in reqs]
+    res = [srv.wait(t, timeout=120) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    print("stats", st, flush=True)
+    assert st["completed"] == len(reqs) and st["peak_active"] > 64
+    s = torch.cuda.Stream()
+    for i in range(0, len(reqs), 7):
+        g, kw = reqs[i]
+        assert same(res[i][0], alone(hp, g, kw, s)), i
