@@ -61,7 +61,8 @@ struct DevState {
     int32_t *par_id;     // [pop][E_S] parent ids of every offspring
     int32_t *gate;       // per offspring: -1 = majority crossover, k = copy of parent k
     unsigned long long *Aq, *Sq;  // fitness accumulators of the offspring
-    int32_t *fr_count;   // final front: size, ids and objectives
+    int32_t *fr_count;   // final front: size, Alg. 3's choice, ids and objectives
+    int32_t *fr_sel;
     int32_t *fr_id;
     int64_t *fr_A, *fr_S;
     double *fr_f1, *fr_f2;

@@ -823,7 +823,19 @@ __global__ __launch_bounds__(SEL_THREADS) void k_final(Span sp)
     if (i == 0) {
         int k = 0;
         for (int j = 0; j < N; ++j) k += sh.rank[j] == 1;
+        // Alg. 3: the first front member (crowded order) of largest Q = (1 - f1) - f2
+        double best = -__builtin_inf();
+        int sel = 0;
+        for (int q = 0; q < k; ++q) {
+            const int src = sh.list[q];
+            const double qv = (1.0 - f1_of(sh.k1[src], m2)) - f2_of(sh.k2[src], m2);
+            if (qv > best) {
+                best = qv;
+                sel = q;
+            }
+        }
         *st.fr_count = k;
+        *st.fr_sel = sel;
     }
 }
 

@@ -80,6 +80,7 @@ RunLayout carve_run(void *ws, int32_t n, int32_t pop, int32_t es, int32_t max_de
     s.Aq = cv.take<unsigned long long>(pop);
     s.Sq = cv.take<unsigned long long>(pop);
     s.fr_count = cv.take<int32_t>(1);
+    s.fr_sel = cv.take<int32_t>(1);
     s.fr_id = cv.take<int32_t>(pop);
     s.fr_A = cv.take<int64_t>(pop);
     s.fr_S = cv.take<int64_t>(pop);
@@ -387,10 +388,12 @@ int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out)
 {
     const RunLayout &L = P.L;
     const int32_t n = P.G->n, pop = P.c.pop;
-    int32_t k = 0;
-    HIP_TRY(hipMemcpyAsync(&k, L.st.fr_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t ks[2] = {0, 0};  // front size and Alg. 3's choice (both computed by k_final)
+    HIP_TRY(hipMemcpyAsync(&ks[0], L.st.fr_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&ks[1], L.st.fr_sel, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (k < 1 || k > pop) return HPMOCD_ERR_HIP;
+    const int32_t k = ks[0];
+    if (k < 1 || k > pop || ks[1] < 0 || ks[1] >= k) return HPMOCD_ERR_HIP;
     HIP_TRY(launch_extract(n, P.c.ld, pop, L.pool[P.cur], L.q[P.cur], L.st.fr_id, k, L.C, s));
     hpmocd_front *f = (hpmocd_front *)std::calloc(1, sizeof(hpmocd_front));
     if (!f) return HPMOCD_ERR_NOMEM;
@@ -415,17 +418,7 @@ int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out)
         hpmocd_front_free(f);
         return HPMOCD_ERR_HIP;
     }
-    // Alg. 3: first maximiser of Q = (1 - f1) - f2
-    double best = -INFINITY;
-    int32_t sel = 0;
-    for (int32_t i = 0; i < k; ++i) {
-        const double qv = (1.0 - f->f1[i]) - f->f2[i];
-        if (qv > best) {
-            best = qv;
-            sel = i;
-        }
-    }
-    f->selected = sel;
+    f->selected = ks[1];
     *out = f;
     return HPMOCD_OK;
 }
