@@ -835,13 +835,10 @@ int hpmocd_resume(const hpmocd_graph *G, const hpmocd_params *p, const hpmocd_sn
         if (sn->labels[i] < 0 || sn->labels[i] >= n) return HPMOCD_ERR_RANGE;
     const int64_t m2 = G->m2;
     std::vector<int32_t> ids(pop);
-    std::vector<double> f1(pop), f2(pop);
     for (int32_t i = 0; i < pop; ++i) {
         if (sn->A[i] < 0 || sn->A[i] > m2 || sn->S[i] < 0 || sn->S[i] > m2 * m2)
             return HPMOCD_ERR_RANGE;
         ids[i] = i;  // member i lives in column i of the committed pool
-        f1[i] = (double)(m2 - sn->A[i]) / (double)m2;   // eq. objectives, as the kernels do
-        f2[i] = (double)sn->S[i] / (double)(m2 * m2);
     }
     if ((rc = check_device(G))) return rc;
     hipStream_t s = (hipStream_t)stream;
@@ -857,8 +854,9 @@ int hpmocd_resume(const hpmocd_graph *G, const hpmocd_params *p, const hpmocd_sn
     HIP_TRY(hipMemcpyAsync(st.ps_id, ids.data(), sizeof(int32_t) * pop, h2d, s));
     HIP_TRY(hipMemcpyAsync(st.ps_A, sn->A, sizeof(int64_t) * pop, h2d, s));
     HIP_TRY(hipMemcpyAsync(st.ps_S, sn->S, sizeof(int64_t) * pop, h2d, s));
-    HIP_TRY(hipMemcpyAsync(st.ps_f1, f1.data(), sizeof(double) * pop, h2d, s));
-    HIP_TRY(hipMemcpyAsync(st.ps_f2, f2.data(), sizeof(double) * pop, h2d, s));
+    // f1, f2 from A, S by the kernels' own divisions (eq. objectives)
+    HIP_TRY(launch_finalize(m2, pop, (const unsigned long long *)st.ps_A,
+                            (const unsigned long long *)st.ps_S, st.ps_f1, st.ps_f2, s));
     HIP_TRY(hipMemcpyAsync(st.gen, &gen, sizeof(int32_t), h2d, s));
     HIP_TRY(B.meta[1].launch(K_CLEAR, s));  // the plain histogram plane starts at zero
     if ((rc = B.generations(sn->g + 1, T, s, s != nullptr, nullptr, nullptr, nullptr, false)))
