@@ -197,6 +197,42 @@ def bench_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_paper_workload(args):
+    """End-to-end wall time (graph creation from host CSR, the run, the front back on the host)
+    on a synthetic stand-in for the paper's LFR graph of 20,000 nodes, whose runtime the paper
+    reports for its own CPU implementation (hardware not stated)."""
+    import numpy as np
+    import torch
+
+    import paper_2506_01752_amd as hp
+    import synth
+
+    g = synth.planted_partition(20000, 20, 50, 0.3, 20, 100, seed=0)
+    params = hp.make_params(pop_size=100, generations=100, crossover_p=0.8, mutation_p=0.2,
+                            parents_per_child=4, seed=0)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    hp.run(hp.Graph(g.row_ptr, g.col), params, stream=stream)   # warm-up
+    walls = []
+    for _ in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        front = hp.run(hp.Graph(g.row_ptr, g.col), params, stream=stream)
+        walls.append(time.perf_counter() - t0)
+    paper_s = 148.36
+    print(json.dumps({
+        "metric": "end-to-end seconds per run (paper's LFR 20k setting)",
+        "value": float(np.median(walls)), "unit": "s", "n_gpus": 1, "steps": len(walls),
+        "higher_is_better": False, "data": "synthetic",
+        "config": {"workload": "planted_partition_20k_mu0.3_paper_setting", "n": g.n, "m": g.m,
+                   "pop_size": 100, "generations": 100, "crossover_p": 0.8, "mutation_p": 0.2,
+                   "parents_per_child": 4},
+        "front_size": int(front.labels.shape[0]),
+        "paper_runtime_s": paper_s, "paper_hardware": "not stated (CPU, multi-threaded Rust)",
+        "ratio_paper_over_this": paper_s / float(np.median(walls)),
+    }), flush=True)
+
+
 def bench_quality(args):
     """Not a speed figure: how well the selected solution (Alg. 3) recovers the planted
     communities, against the best partition of the initial population."""
@@ -396,6 +432,10 @@ def main():
                     help="solution-quality sanity instead: agreement of the selected solution "
                          "with the planted partition at |V| = 1,000 (5 seeds) and |V| = 40,000 "
                          "(mu sweep)")
+    ap.add_argument("--paper-workload", action="store_true",
+                    help="the paper's LFR setting (n 20,000, mean degree 20, max 50, communities "
+                         "20-100, mu 0.3; pop 100, 100 generations, C_P 0.8, M_P 0.2, E_S 4) end "
+                         "to end, next to the paper's reported runtime")
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -422,6 +462,8 @@ def main():
         return bench_served(args)
     if args.quality:
         return bench_quality(args)
+    if args.paper_workload:
+        return bench_paper_workload(args)
 
     import torch
 
