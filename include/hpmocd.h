@@ -30,7 +30,7 @@ extern "C" {
 #define HPMOCD_ERR_CSR_ASYM -2   /* arc (u,v) present without (v,u) */
 #define HPMOCD_ERR_SELF_LOOP -3  /* arc (v,v); section 2.1 excludes self-loops */
 #define HPMOCD_ERR_DUP_EDGE -4   /* repeated arc; the graph is simple (section 2.1) */
-#define HPMOCD_ERR_RANGE -5      /* row_ptr not monotone from 0, or a column outside [0,n) */
+#define HPMOCD_ERR_RANGE -5      /* row_ptr not monotone from 0, or a column or label outside [0,n) */
 #define HPMOCD_ERR_EMPTY -6      /* no edge: f1 = 0/0 is undefined */
 #define HPMOCD_ERR_TOO_LARGE -7  /* (2m)^2 > 2^53: f2's denominator would not be exact */
 #define HPMOCD_ERR_WORKSPACE -8  /* workspace smaller than the size the library asked for */
@@ -183,8 +183,9 @@ int hpmocd_resume(const hpmocd_graph *g, const hpmocd_params *p, const hpmocd_sn
 void hpmocd_snapshot_free(hpmocd_snapshot *s);
 
 /* Fitness alone (eq. objectives) for n_ind partitions given as device memory, row-major
- * n_ind x n int32 labels in [0, n) (values outside are an error the kernel cannot report:
- * the caller guarantees the range). Writes A, S, f1, f2 (host arrays of n_ind). */
+ * n_ind x n int32 labels in [0, n). Writes A, S, f1, f2 (host arrays of n_ind). A label
+ * outside [0, n) gives HPMOCD_ERR_RANGE (found while the labels are read; the outputs are then
+ * not written). */
 int hpmocd_eval_workspace_size(const hpmocd_graph *g, int32_t n_ind, size_t *bytes);
 int hpmocd_eval(const hpmocd_graph *g, const int32_t *d_labels, int32_t n_ind,
                 void *d_workspace, size_t ws_bytes, void *stream, int64_t *A, int64_t *S,
@@ -251,7 +252,9 @@ int hpmocd_server_submit(hpmocd_server *s, int32_t n, const int32_t *row_ptr, co
 int hpmocd_server_poll(hpmocd_server *s, int64_t ticket, int32_t *state);
 /* Blocks until the request is done or timeout_s passes (< 0: no limit). On completion
  * returns the request's status and releases the ticket; on HPMOCD_OK *out receives the front
- * (free with hpmocd_front_free) and *info (may be NULL) its timings. */
+ * (free with hpmocd_front_free) and *info (may be NULL) its timings. Several threads may wait
+ * on one ticket: the first to see it done consumes it, the others return HPMOCD_ERR_ARG, as
+ * does any later call with that ticket. */
 int hpmocd_server_wait(hpmocd_server *s, int64_t ticket, double timeout_s, hpmocd_front **out,
                        hpmocd_request_info *info);
 /* A queued request is dropped at once, a resident one at the next step; its wait returns

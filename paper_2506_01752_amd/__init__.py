@@ -23,6 +23,8 @@ ERR = {
     -9: "ERR_HIP", -10: "ERR_BUDGET", -11: "ERR_NOMEM", -12: "ERR_CANCELLED",
     -13: "ERR_TIMEOUT",
 }
+ERR_ARG = -1
+ERR_RANGE = -5
 ERR_BUDGET = -10
 ERR_CANCELLED = -12
 ERR_TIMEOUT = -13

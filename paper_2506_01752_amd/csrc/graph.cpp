@@ -212,7 +212,7 @@ const char *hpmocd_strerror(int status)
     case HPMOCD_ERR_CSR_ASYM: return "CSR is not symmetric";
     case HPMOCD_ERR_SELF_LOOP: return "graph has a self-loop";
     case HPMOCD_ERR_DUP_EDGE: return "graph has a repeated edge";
-    case HPMOCD_ERR_RANGE: return "row_ptr or column index out of range";
+    case HPMOCD_ERR_RANGE: return "row_ptr, column index or label out of range";
     case HPMOCD_ERR_EMPTY: return "graph has no edge";
     case HPMOCD_ERR_TOO_LARGE: return "(2m)^2 exceeds 2^53";
     case HPMOCD_ERR_WORKSPACE: return "workspace too small";

@@ -28,6 +28,14 @@ namespace hpm {
         if (e_ != hipSuccess) return HPMOCD_ERR_HIP;    \
     } while (0)
 
+// Waits for stream s when it leaves scope: an entry point that returns early on an error
+// leaves no kernel running on memory its caller may free next (on success s is already
+// drained, so the wait costs nothing).
+struct DrainOnExit {
+    hipStream_t s;
+    ~DrainOnExit() { (void)hipStreamSynchronize(s); }
+};
+
 // A validated graph on the host: sorted adjacency and the mutation kernels' degree classes.
 struct HostGraph {
     int32_t n = 0;

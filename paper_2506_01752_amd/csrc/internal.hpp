@@ -146,8 +146,10 @@ hipError_t launch_kind(Kind k, const Span &sp, int32_t blocks, size_t lds, int32
 hipError_t launch_extract(int32_t n, int32_t ld, int32_t pop, const int32_t *pool,
                           const int32_t *q, const int32_t *ids, int32_t k, int32_t *out,
                           hipStream_t s);
+// bad (may be null): a device flag set to 1 if a label lies outside [0, n); such labels are
+// stored as 0
 hipError_t launch_transpose_in(const int32_t *rows, int32_t n, int32_t n_ind, int32_t ld,
-                               int32_t *out, hipStream_t s);
+                               int32_t *out, int32_t *bad, hipStream_t s);
 hipError_t launch_finalize(int64_t m2, int32_t n_ind, const unsigned long long *A,
                            const unsigned long long *S, double *f1, double *f2,
                            hipStream_t s);

@@ -1496,9 +1496,10 @@ hipError_t launch_extract(int32_t n, int32_t ld, int32_t pop, const int32_t *poo
     return hipGetLastError();
 }
 
-// rows [n_ind][n] -> node-major [n][ld], 32x32 tiles through LDS
+// rows [n_ind][n] -> node-major [n][ld], 32x32 tiles through LDS. With `bad`, a label
+// outside [0, n) is stored as 0 (the kernels downstream index by label) and *bad set to 1.
 __global__ void k_transpose_in(const int32_t *__restrict__ rows, int32_t n, int32_t n_ind,
-                               int32_t ld, int32_t *__restrict__ out)
+                               int32_t ld, int32_t *__restrict__ out, int32_t *__restrict__ bad)
 {
     __shared__ int tile[32][33];
     const int64_t v0 = (int64_t)blockIdx.x * 32;
@@ -1506,7 +1507,14 @@ __global__ void k_transpose_in(const int32_t *__restrict__ rows, int32_t n, int3
     for (int r = threadIdx.y; r < 32; r += blockDim.y) {
         const int i = i0 + r;
         const int64_t v = v0 + threadIdx.x;
-        if (i < n_ind && v < n) tile[r][threadIdx.x] = rows[(size_t)i * n + v];
+        if (i < n_ind && v < n) {
+            int32_t x = rows[(size_t)i * n + v];
+            if (bad && (x < 0 || x >= n)) {
+                *bad = 1;
+                x = 0;
+            }
+            tile[r][threadIdx.x] = x;
+        }
     }
     __syncthreads();
     for (int r = threadIdx.y; r < 32; r += blockDim.y) {
@@ -1517,10 +1525,10 @@ __global__ void k_transpose_in(const int32_t *__restrict__ rows, int32_t n, int3
 }
 
 hipError_t launch_transpose_in(const int32_t *rows, int32_t n, int32_t n_ind, int32_t ld,
-                               int32_t *out, hipStream_t s)
+                               int32_t *out, int32_t *bad, hipStream_t s)
 {
     dim3 grid((unsigned)((n + 31) / 32), (unsigned)((n_ind + 31) / 32));
-    k_transpose_in<<<grid, dim3(32, 8), 0, s>>>(rows, n, n_ind, ld, out);
+    k_transpose_in<<<grid, dim3(32, 8), 0, s>>>(rows, n, n_ind, ld, out, bad);
     return hipGetLastError();
 }
 

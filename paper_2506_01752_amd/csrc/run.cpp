@@ -259,7 +259,10 @@ int Fork::init()
 Fork::~Fork()
 {
     for (int i = 0; i < 2; ++i) {
-        if (side[i]) (void)hipStreamDestroy(side[i]);
+        if (side[i]) {
+            (void)hipStreamSynchronize(side[i]);  // work left unjoined by an error path
+            (void)hipStreamDestroy(side[i]);
+        }
         if (join[i]) (void)hipEventDestroy(join[i]);
     }
     if (fork) (void)hipEventDestroy(fork);
@@ -602,6 +605,7 @@ int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_par
     for (int32_t i = 0; i < count; ++i)
         if ((rc = check_device(graphs[i]))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    DrainOnExit drain{s};
     const int32_t T = params[0].generations;
     const bool autotune_on = (flags & HPMOCD_AUTOTUNE) != 0;
     Tuning t;
@@ -788,6 +792,7 @@ int hpmocd_run_to(const hpmocd_graph *G, const hpmocd_params *p, int32_t stop_ge
     if (stop_gen < 0 || stop_gen > p->generations) return HPMOCD_ERR_ARG;
     if ((rc = check_device(G))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    DrainOnExit drain{s};
     Batch B;
     if ((rc = B.setup(&G, 1, p, ws, ws_bytes, Tuning{}, false, s))) return rc;
     HIP_TRY(launch_init_seq(B.meta[0], s, &B.fork));
@@ -842,6 +847,7 @@ int hpmocd_resume(const hpmocd_graph *G, const hpmocd_params *p, const hpmocd_sn
     }
     if ((rc = check_device(G))) return rc;
     hipStream_t s = (hipStream_t)stream;
+    DrainOnExit drain{s};
     Batch B;
     if ((rc = B.setup(&G, 1, p, ws, ws_bytes, Tuning{}, false, s))) return rc;
     Pop &P = B.pops[0];
@@ -850,7 +856,7 @@ int hpmocd_resume(const hpmocd_graph *G, const hpmocd_params *p, const hpmocd_sn
     const int32_t gen = sn->g + 1;  // the device generation counter after selection of g
     const hipMemcpyKind h2d = hipMemcpyHostToDevice;
     HIP_TRY(hipMemcpyAsync(P.L.C, sn->labels, sizeof(int32_t) * (size_t)pop * n, h2d, s));
-    HIP_TRY(launch_transpose_in(P.L.C, n, pop, P.c.ld, P.L.pool[0], s));
+    HIP_TRY(launch_transpose_in(P.L.C, n, pop, P.c.ld, P.L.pool[0], nullptr, s));  // checked above
     HIP_TRY(hipMemcpyAsync(st.ps_id, ids.data(), sizeof(int32_t) * pop, h2d, s));
     HIP_TRY(hipMemcpyAsync(st.ps_A, sn->A, sizeof(int64_t) * pop, h2d, s));
     HIP_TRY(hipMemcpyAsync(st.ps_S, sn->S, sizeof(int64_t) * pop, h2d, s));
@@ -877,6 +883,7 @@ int hpmocd_eval_workspace_size(const hpmocd_graph *g, int32_t n_ind, size_t *byt
     size_t b = align_up((size_t)g->n * ld * 4);  // transposed labels
     b += hp.enabled ? align_up(hp.entries * 4) + align_up(hp.offsets * 4) : align_up((size_t)g->n * ld * 4);
     b += 2 * align_up(8 * (size_t)n_ind) + 2 * align_up(8 * (size_t)n_ind);
+    b += align_up(sizeof(int32_t));  // out-of-range label flag
     b += meta_bytes(1);
     *bytes = b;
     return HPMOCD_OK;
@@ -893,6 +900,7 @@ int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, v
     hpmocd_eval_workspace_size(G, n_ind, &need);
     if (ws_bytes < need) return HPMOCD_ERR_WORKSPACE;
     hipStream_t s = (hipStream_t)stream;
+    DrainOnExit drain{s};
     const int32_t ld = round16(n_ind);
     const size_t plane = (size_t)G->n * ld * 4;
     char *p = (char *)ws;
@@ -919,6 +927,8 @@ int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, v
     p += align_up(8 * (size_t)n_ind);
     double *df2 = (double *)p;
     p += align_up(8 * (size_t)n_ind);
+    int32_t *d_bad = (int32_t *)p;
+    p += align_up(sizeof(int32_t));
     it.lab = lab;
     it.fit_pop = n_ind;
     it.fit_ld = ld;
@@ -933,7 +943,8 @@ int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, v
     if ((rc = m.upload(items, p, s))) return rc;
     HIP_TRY(m.launch(K_CLEAR, s));
     HIP_TRY(m.one(ONE_ZERO_ACC, s));
-    HIP_TRY(launch_transpose_in(d_labels, G->n, n_ind, ld, lab, s));
+    HIP_TRY(hipMemsetAsync(d_bad, 0, sizeof(int32_t), s));
+    HIP_TRY(launch_transpose_in(d_labels, G->n, n_ind, ld, lab, d_bad, s));
     EventSet evs;
     hipEvent_t a = nullptr, b = nullptr;
     if (kernel_ms) {
@@ -946,11 +957,14 @@ int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, v
     if (kernel_ms) HIP_TRY(hipEventRecord(b, s));
     HIP_TRY(launch_finalize(G->m2, n_ind, dA, dS, df1, df2, s));
     std::vector<unsigned long long> hA(n_ind), hS(n_ind);
+    int32_t bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(hA.data(), dA, sizeof(unsigned long long) * n_ind, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(hS.data(), dS, sizeof(unsigned long long) * n_ind, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(f1, df1, sizeof(double) * n_ind, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(f2, df2, sizeof(double) * n_ind, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (bad) return HPMOCD_ERR_RANGE;  // evaluated with those labels replaced by 0
     for (int32_t i = 0; i < n_ind; ++i) {
         A[i] = (int64_t)hA[i];
         S[i] = (int64_t)hS[i];

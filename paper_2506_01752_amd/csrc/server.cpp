@@ -460,15 +460,21 @@ int hpmocd_server_wait(hpmocd_server *s, int64_t ticket, double timeout_s, hpmoc
 {
     if (!s || !out) return HPMOCD_ERR_ARG;
     std::unique_lock<std::mutex> lk(s->mu);
+    if (s->reqs.find(ticket) == s->reqs.end()) return HPMOCD_ERR_ARG;
+    // looked up again at every wake-up: another thread's wait on the same ticket may have
+    // consumed it meanwhile
+    auto settled = [&] {
+        auto i = s->reqs.find(ticket);
+        return i == s->reqs.end() || i->second->state == HPMOCD_REQ_DONE;
+    };
+    if (timeout_s < 0) {
+        s->cv_done.wait(lk, settled);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), settled)) {
+        return HPMOCD_ERR_TIMEOUT;
+    }
     auto it = s->reqs.find(ticket);
     if (it == s->reqs.end()) return HPMOCD_ERR_ARG;
     Request *r = it->second.get();
-    auto done = [&] { return r->state == HPMOCD_REQ_DONE; };
-    if (timeout_s < 0) {
-        s->cv_done.wait(lk, done);
-    } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), done)) {
-        return HPMOCD_ERR_TIMEOUT;
-    }
     const int st = r->status;
     if (st == HPMOCD_OK) {
         *out = r->front;

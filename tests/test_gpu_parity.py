@@ -90,6 +90,26 @@ def test_eval_matches_oracle(hp, stream, gname, n_ind):
         assert bits([f1[i]])[0] == bits([r1])[0] and bits([f2[i]])[0] == bits([r2])[0]
 
 
+@pytest.mark.parametrize("bad", [-1, 1000, 2**31 - 1])
+def test_eval_out_of_range_label_is_an_error(hp, stream, bad):
+    """A label outside [0, n) is reported as ERR_RANGE (the kernel that reads the labels
+    replaces it by 0 before any label-indexed access); valid labels evaluated afterwards on the
+    same graph are unaffected."""
+    import torch
+    g = synth.small_1k()
+    say(f"eval out-of-range label {bad}")
+    dg = hp.Graph(g.row_ptr, g.col)
+    labs = np.zeros((3, g.n), dtype=np.int32)
+    labs[1, 17] = bad
+    with pytest.raises(hp.HpmocdError) as e:
+        hp.evaluate(dg, torch.from_numpy(labs).cuda(), stream=stream)
+    assert e.value.status == hp.ERR_RANGE
+    ok = np.stack([g.membership, np.arange(g.n)]).astype(np.int32)
+    A, S, f1, f2 = hp.evaluate(dg, torch.from_numpy(ok).cuda(), stream=stream)
+    for i in range(2):
+        assert (A[i], S[i]) == oracle.evaluate(g.row_ptr, g.col, ok[i])[:2]
+
+
 # ---------------------------------------------------------------------------------------
 # whole runs, traced every generation
 # ---------------------------------------------------------------------------------------

@@ -216,3 +216,36 @@ def test_server_many_small_requests_wide_tables(hp):
     for i in range(0, len(reqs), 7):
         g, kw = reqs[i]
         assert same(res[i][0], alone(hp, g, kw, s)), i
+
+
+def test_server_two_waiters_on_one_ticket(hp):
+    """Two threads wait on one ticket: one receives the front, the other ERR_ARG (the ticket
+    was consumed), and so does any later call with it."""
+    import torch
+    g = synth.small_1k()
+    kw = dict(pop_size=32, generations=6, seed=5)
+    srv = hp.Server(hbm_budget=1 << 30, max_active=4)
+    t, _ = srv.submit(g.row_ptr, g.col, **kw)
+    got = [None, None]
+
+    def waiter(i):
+        try:
+            got[i] = ("front", srv.wait(t, timeout=120)[0])
+        except hp.HpmocdError as e:
+            got[i] = ("error", e.status)
+
+    th = [threading.Thread(target=waiter, args=(i,)) for i in range(2)]
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    kinds = sorted(k for k, _ in got)
+    assert kinds == ["error", "front"], got
+    err = [v for k, v in got if k == "error"][0]
+    front = [v for k, v in got if k == "front"][0]
+    assert err == hp.ERR_ARG
+    with pytest.raises(hp.HpmocdError) as e:
+        srv.poll(t)
+    assert e.value.status == hp.ERR_ARG
+    srv.close()
+    assert same(front, alone(hp, g, kw, torch.cuda.Stream()))
