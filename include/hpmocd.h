@@ -142,6 +142,14 @@ int hpmocd_run_ex(const hpmocd_graph *g, const hpmocd_params *p, void *d_workspa
                   size_t ws_bytes, void *stream, int flags, hpmocd_profile *profile,
                   hpmocd_trace_fn trace, void *user, hpmocd_front **out);
 
+/* hpmocd_run with a per-generation trace (tests only): on_generation receives the initial
+ * population (g = 0) and the population after every generation's environmental selection,
+ * copied to the host (kernels launched one by one, a device-to-host copy per generation).
+ * The front equals hpmocd_run's. Same as hpmocd_run_ex with flags 0 and no profile. */
+int hpmocd_run_traced(const hpmocd_graph *g, const hpmocd_params *p, void *d_workspace,
+                      size_t ws_bytes, void *stream, hpmocd_trace_fn on_generation, void *user,
+                      hpmocd_front **out);
+
 void hpmocd_front_free(hpmocd_front *f);
 
 /* Batched form: `count` independent runs of Alg. 1, each on its own graph with its own

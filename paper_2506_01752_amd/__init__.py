@@ -40,7 +40,8 @@ REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 # every entry point that include/hpmocd.h declares
 EXPORTS = [
     "hpmocd_graph_create", "hpmocd_graph_destroy", "hpmocd_graph_info",
-    "hpmocd_workspace_size", "hpmocd_run", "hpmocd_run_ex", "hpmocd_front_free",
+    "hpmocd_workspace_size", "hpmocd_run", "hpmocd_run_ex", "hpmocd_run_traced",
+    "hpmocd_front_free",
     "hpmocd_eval_workspace_size", "hpmocd_eval", "hpmocd_strerror",
     "hpmocd_batch_workspace_size", "hpmocd_run_batch",
     "hpmocd_server_arena_overhead", "hpmocd_server_create", "hpmocd_server_submit",
@@ -142,6 +143,8 @@ def lib():
         L.hpmocd_run_ex.argtypes = [vp, C.POINTER(Params), vp, C.c_size_t, vp, C.c_int,
                                     C.POINTER(Profile), _TRACE, vp,
                                     C.POINTER(C.POINTER(_Front))]
+        L.hpmocd_run_traced.argtypes = [vp, C.POINTER(Params), vp, C.c_size_t, vp, _TRACE, vp,
+                                        C.POINTER(C.POINTER(_Front))]
         L.hpmocd_front_free.argtypes = [C.POINTER(_Front)]
         L.hpmocd_front_free.restype = None
         L.hpmocd_eval_workspace_size.argtypes = [vp, C.c_int32, C.POINTER(C.c_size_t)]
@@ -321,10 +324,15 @@ def run(graph: Graph, params: Params | None = None, *, stream=None, workspace=No
                 np.ctypeslib.as_array(v.rank, shape=(np_,)).copy() if v.rank else None,
                 np.ctypeslib.as_array(v.crowd, shape=(np_,)).copy() if v.crowd else None))
         cb = _TRACE(_cb)
-    st = lib().hpmocd_run_ex(graph.handle, C.byref(params), C.c_void_p(ws.data_ptr()), nbytes,
-                             _stream_handle(stream), flags,
-                             C.byref(prof) if profile else None, cb, None, C.byref(out))
-    _check(st, "hpmocd_run_ex")
+    if on_generation is not None and not flags and not profile:
+        st = lib().hpmocd_run_traced(graph.handle, C.byref(params), C.c_void_p(ws.data_ptr()),
+                                     nbytes, _stream_handle(stream), cb, None, C.byref(out))
+        _check(st, "hpmocd_run_traced")
+    else:
+        st = lib().hpmocd_run_ex(graph.handle, C.byref(params), C.c_void_p(ws.data_ptr()),
+                                 nbytes, _stream_handle(stream), flags,
+                                 C.byref(prof) if profile else None, cb, None, C.byref(out))
+        _check(st, "hpmocd_run_ex")
     front = _front_from(out)
     return (front, prof.as_dict()) if profile else front
 

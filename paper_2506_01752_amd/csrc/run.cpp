@@ -753,6 +753,14 @@ int hpmocd_run(const hpmocd_graph *g, const hpmocd_params *p, void *ws, size_t w
     return hpmocd_run_ex(g, p, ws, ws_bytes, stream, 0, nullptr, nullptr, nullptr, out);
 }
 
+int hpmocd_run_traced(const hpmocd_graph *g, const hpmocd_params *p, void *ws, size_t ws_bytes,
+                      void *stream, hpmocd_trace_fn on_generation, void *user,
+                      hpmocd_front **out)
+{
+    if (!on_generation) return HPMOCD_ERR_ARG;
+    return hpmocd_run_ex(g, p, ws, ws_bytes, stream, 0, nullptr, on_generation, user, out);
+}
+
 int hpmocd_batch_workspace_size(const hpmocd_graph *const *graphs, int32_t count,
                                 const hpmocd_params *params, int flags, size_t *bytes)
 {
