@@ -1177,17 +1177,11 @@ __device__ __forceinline__ void wave_bitonic(int (&a)[E])
     }
 }
 
+// Plurality of the d labels a[] holds (position lane + 64k, INT_MAX beyond d); sorts a.
 template <int E>
-__device__ __forceinline__ int wave_plurality(const GLB int32_t *__restrict__ C, int ld, int j,
-                                              const GLB int32_t *__restrict__ nbr, int d, uint32_t r)
+__device__ __forceinline__ int wave_resolve(int (&a)[E], int d, uint32_t r)
 {
     const int lane = lane_id();
-    int a[E];
-#pragma unroll
-    for (int k = 0; k < E; ++k) {
-        const int p = lane + 64 * k;
-        a[k] = p < d ? C[(size_t)nbr[p] * ld + j] : INT_MAX;
-    }
     wave_bitonic<E>(a);
     uint64_t St[E];
 #pragma unroll
@@ -1243,21 +1237,32 @@ __device__ __forceinline__ int wave_plurality(const GLB int32_t *__restrict__ C,
 }
 
 // Degree class (64(E/2), 64E]: a wave takes one node and a slice of its offspring, draws
-// their MUT words, queues the mutating ones in LDS and resolves them one at a time with the
-// wave sort.
+// their MUT words, queues the mutating ones in LDS and resolves them in batches: the labels
+// of a batch's items are gathered together (each lane reads the batch's columns of one
+// neighbour row back to back, so a row line is fetched once per batch, not once per item),
+// then each item is sorted and resolved in turn.
 //
 // Waves per node in the wave classes: a node's offspring are split into this many slices so
 // that one wave resolves about `per` mutations (a node has pop * M_P of them on average). One
 // wave per node left the few high-degree nodes' waves resolving ten or more wave-wide sorts
-// one after another while the rest of the chip idled.
+// one after another while the rest of the chip idled. The count is a power of two up to
+// MUT_WAVES, so all slices of a node fall in one workgroup and its waves read the node's
+// neighbour rows at the same time, through one L2, instead of from up to three XCDs.
 __host__ __device__ inline int mut_slices(int cls, int pop, uint64_t thr_m)
 {
     if (cls < 2) return 1;
     const int per = cls == 2 ? 8 : (cls == 3 ? 4 : (cls == 4 ? 2 : 1));
     const int expect = (int)(((uint64_t)pop * thr_m) >> 32);  // floor(pop * M_P)
-    const int sl = expect / per;
-    return sl < 1 ? 1 : (sl > pop ? pop : sl);
+    int sl = 1;
+    while (sl < MUT_WAVES && sl * 2 <= expect / per && sl * 2 <= pop) sl *= 2;
+    return sl;
 }
+
+// items per gather batch: B x E labels held per lane
+template <int E>
+struct WaveBatch {
+    static constexpr int B = E <= 4 ? 8 : (E == 8 ? 4 : (E == 16 ? 2 : 1));
+};
 
 template <int E>
 __global__ __launch_bounds__(256) void k_mutate_wave(Span sp, int cls)
@@ -1300,10 +1305,27 @@ __global__ __launch_bounds__(256) void k_mutate_wave(Span sp, int cls)
             count += __popcll(bal);
         }
         wave_lds_sync();
-        for (int it = 0; it < count; ++it) {
-            const uint2 item = items[wv][it];
-            const int out = wave_plurality<E>(C, ld, (int)item.x, nbr, d, item.y);
-            if (lane == 0) q_next[(size_t)node * ld + item.x] = out;
+        constexpr int B = WaveBatch<E>::B;
+        for (int i0 = 0; i0 < count; i0 += B) {
+            const int nb = min(B, count - i0);
+            int jb[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) jb[b] = b < nb ? (int)items[wv][i0 + b].x : 0;
+            int a[B][E];
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                const int p = lane + 64 * k;
+                const size_t row = p < d ? (size_t)nbr[p] * ld : 0;
+#pragma unroll
+                for (int b = 0; b < B; ++b) a[b][k] = (p < d && b < nb) ? C[row + jb[b]] : INT_MAX;
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                if (b < nb) {
+                    const int out = wave_resolve<E>(a[b], d, items[wv][i0 + b].y);
+                    if (lane == 0) q_next[(size_t)node * ld + jb[b]] = out;
+                }
+            }
         }
         wave_lds_sync();
     }

@@ -268,9 +268,9 @@ Fork::~Fork()
     if (fork) (void)hipEventDestroy(fork);
 }
 
-// Mutation launches of one generation. With a fork: degree classes <= 16 and 513-1024 on s,
-// 17-32, 33-64 and 257-512 on the first side stream, the rest on the second (a rough split
-// of their measured times), joined back into s.
+// Mutation launches of one generation. With a fork: degree class <= 16 on s, 17-32 and 33-64
+// on the first side stream, the rest on the second (a split of their measured times at
+// |V| = 1M: about 1.2, 1.1 and 1.0 ms), joined back into s.
 static hipError_t launch_mutation(const Meta &m, hipStream_t s, const Fork *fk)
 {
     hipError_t e;
@@ -279,7 +279,7 @@ static hipError_t launch_mutation(const Meta &m, hipStream_t s, const Fork *fk)
             if ((e = m.launch((Kind)(K_MUT0 + k), s)) != hipSuccess) return e;
         return m.launch(K_MUTL, s);
     }
-    static const int group[N_DEG_CLASSES] = {0, 1, 1, 2, 2, 1, 0, 2};
+    static const int group[N_DEG_CLASSES] = {0, 1, 1, 2, 2, 2, 2, 2};
     if ((e = hipEventRecord(fk->fork, s)) != hipSuccess) return e;
     for (int i = 0; i < 2; ++i)
         if ((e = hipStreamWaitEvent(fk->side[i], fk->fork, 0)) != hipSuccess) return e;
