@@ -185,8 +185,10 @@ def test_high_degree_mutation_paths(hp, stream):
     g = synth.csr_from_edges(n, np.concatenate([np.array(edges), extra]))
     deg = np.diff(g.row_ptr)
     say(f"hubs n={g.n} degrees={sorted(deg)[-8:]}")
-    for mp, seed in [(0.6, 5), (1.0, 6)]:
-        got, ref, gs, os_ = traced_pair(hp, stream, g, threads=4, pop_size=20, generations=3,
+    # pop 100 at M_P 1.0 fills every per-wave gather batch several times over (up to 25
+    # mutations per slice), pop 20 leaves them partly empty
+    for mp, seed, pop in [(0.6, 5, 20), (1.0, 6, 20), (1.0, 7, 100), (0.3, 8, 100)]:
+        got, ref, gs, os_ = traced_pair(hp, stream, g, threads=4, pop_size=pop, generations=3,
                                         mutation_p=mp, seed=seed)
         assert_states_equal(gs, os_)
         assert_front_equal(got, ref)
