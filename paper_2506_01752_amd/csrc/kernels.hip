@@ -493,6 +493,9 @@ __global__ __launch_bounds__(256) void k_hist(Span sp)
     const GLB uint32_t *__restrict__ off = glb(it.off);
     GLB unsigned long long *__restrict__ S = glb(it.fit_S);
     extern __shared__ uint32_t hist[];  // [2^rbits], the whole 64 KB at most
+    // the arc scan runs beside this kernel; its waves are bandwidth-bound while these wait on
+    // chains of dependent loads, so these take the higher issue priority on a shared CU
+    __builtin_amdgcn_s_setprio(3);
     // individuals of one tile side by side: the 16 of a group read adjacent run offsets
     const int lg = xcd_remap(lb, nblk);
     const int t = lg / it.fit_pop, j = lg % it.fit_pop;
