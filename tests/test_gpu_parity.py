@@ -266,3 +266,27 @@ def test_random_sweep_against_oracle(hp, stream):
         got = hp.run(hp.Graph(g.row_ptr, g.col), stream=stream, **kw)
         ref = oracle.run(g.row_ptr, g.col, threads=4, **kw)
         assert_front_equal(got, ref)
+
+
+def test_random_hub_graphs_against_oracle(hp, stream):
+    """Seeded random graphs with hubs in every per-wave and LDS mutation class (degrees up to
+    ~2600) under random populations and rates, so that the per-wave gather batches run full,
+    partial and split over 1, 2 or 4 slices; every front bit-exact against the oracle."""
+    rng = np.random.default_rng(77)
+    for case in range(12):
+        n = int(rng.integers(800, 4000))
+        edges = []
+        for h in range(int(rng.integers(2, 7))):
+            deg = int(min(n - 10, rng.choice([40, 90, 200, 400, 900, 1500, 2600])))
+            nb = rng.choice(np.arange(10, n), size=deg, replace=False)
+            edges += [(h, int(u)) for u in nb]
+        extra = rng.integers(10, n, size=(int(rng.integers(n, 4 * n)), 2))
+        g = synth.csr_from_edges(n, np.concatenate([np.array(edges), extra]))
+        kw = dict(pop_size=int(rng.choice([7, 33, 100, 160])), generations=int(rng.integers(1, 4)),
+                  crossover_p=float(rng.choice([0.5, 0.9])),
+                  mutation_p=float(rng.choice([0.05, 0.2, 0.5, 1.0])),
+                  parents_per_child=int(rng.integers(2, 6)), seed=int(rng.integers(0, 2**62)))
+        say(f"hub case {case}: n={g.n} m={g.m} max_deg={int(np.diff(g.row_ptr).max())} {kw}")
+        got = hp.run(hp.Graph(g.row_ptr, g.col), stream=stream, **kw)
+        ref = oracle.run(g.row_ptr, g.col, threads=4, **kw)
+        assert_front_equal(got, ref)
