@@ -257,7 +257,8 @@ def bench_quality(args):
                        **dict(synth.GA_DEFAULT, seed=seed))
         sel = front.labels[front.selected]
         best0 = max(q.nmi(row, g.membership) for row in init["labels"])
-        return {"nmi": q.nmi(sel, g.membership), "ari": q.ari(sel, g.membership),
+        return {"nmi": q.nmi(sel, g.membership), "ami": q.ami(sel, g.membership),
+                "ari": q.ari(sel, g.membership),
                 "pair_f1": q.pair_f1(sel, g.membership),
                 "q": q.modularity(front.f1[front.selected], front.f2[front.selected]),
                 "front_size": int(front.labels.shape[0]),

@@ -1,5 +1,7 @@
-"""Partition-agreement measures (reporting tools): pinned to closed forms and, where
-scikit-learn is importable, to its implementations."""
+"""Partition-agreement measures (reporting tools): pinned to closed forms, brute force and,
+where scikit-learn is importable, to its implementations."""
+import itertools
+
 import numpy as np
 import pytest
 
@@ -10,6 +12,7 @@ def test_identical_up_to_renaming():
     a = np.array([0, 0, 1, 1, 2, 2, 2])
     b = np.array([7, 7, 3, 3, 9, 9, 9])
     assert q.nmi(a, b) == pytest.approx(1.0)
+    assert q.ami(a, b) == pytest.approx(1.0)
     assert q.ari(a, b) == pytest.approx(1.0)
     assert q.pair_f1(a, b) == pytest.approx(1.0)
 
@@ -60,8 +63,44 @@ def test_against_sklearn_random():
         b = rng.integers(0, int(rng.integers(1, 30)), size=n)
         assert q.nmi(a, b) == pytest.approx(metrics.normalized_mutual_info_score(a, b), abs=1e-9)
         assert q.ari(a, b) == pytest.approx(metrics.adjusted_rand_score(a, b), abs=1e-9)
+        assert q.ami(a, b) == pytest.approx(
+            metrics.adjusted_mutual_info_score(a, b, average_method="max"), abs=1e-9)
 
 
 def test_modularity_matches_fig1_closed_form():
     # Fig. 1 graph, natural split: f1 = 1/21, f2 = 1/2, Q = 19/42
     assert q.modularity(1 / 21, 1 / 2) == pytest.approx(19 / 42)
+
+
+def _mi(a, b):
+    c = q._contingency(a, b)
+    n = c.sum()
+    ra, rb = c.sum(1), c.sum(0)
+    return sum(c[i, j] / n * np.log(c[i, j] * n / (ra[i] * rb[j]))
+               for i in range(c.shape[0]) for j in range(c.shape[1]) if c[i, j] > 0)
+
+
+@pytest.mark.parametrize("a,b", [([0, 0, 0, 1, 1, 2, 2], [0, 1, 1, 1, 2, 2, 2]),
+                                 ([0, 0, 1, 1, 1, 1], [0, 1, 0, 1, 0, 2]),
+                                 ([0, 1, 2, 3, 0, 1], [5, 5, 5, 6, 6, 6])])
+def test_ami_expectation_by_brute_force(a, b):
+    """E[MI] is the mean MI over every relabelling of b's items (all n! orders), so AMI follows
+    from the definition of section 5 with no library in the loop."""
+    a, b = np.array(a), np.array(b)
+    perms = itertools.permutations(range(len(b)))
+    emi = float(np.mean([_mi(a, b[list(p)]) for p in perms]))
+    c = q._contingency(a, b)
+    assert q._expected_mi(c.sum(1), c.sum(0), c.sum()) == pytest.approx(emi, rel=1e-12)
+    n = len(a)
+    h = lambda x: -sum(k / n * np.log(k / n) for k in np.unique(x, return_counts=True)[1])
+    want = (_mi(a, b) - emi) / (max(h(a), h(b)) - emi)
+    assert q.ami(a, b) == pytest.approx(want, rel=1e-10)
+
+
+def test_ami_is_zero_on_average_for_independent_partitions():
+    rng = np.random.default_rng(3)
+    vals = [q.ami(rng.integers(0, 6, size=60), rng.integers(0, 4, size=60)) for _ in range(300)]
+    assert abs(np.mean(vals)) < 0.01
+    assert q.ami(np.zeros(9, dtype=int), np.zeros(9, dtype=int)) == 1.0
+    assert q.ami(np.arange(9), np.arange(9)[::-1]) == 1.0
+
