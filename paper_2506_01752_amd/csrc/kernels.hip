@@ -228,6 +228,7 @@ __global__ __launch_bounds__(256) void k_init(Span sp)
 // order the atomics take.
 // ---------------------------------------------------------------------------------------
 constexpr int FIT_ARCS = 16;   // arcs in flight per wave in the scan phase
+constexpr int FIT_WAVES = 4;   // waves per k_fitness workgroup
 constexpr int FIT_NODES = 8;   // nodes per batch in the histogram phase
 
 __device__ __forceinline__ unsigned long long sq_step(int old, int d)
@@ -242,27 +243,29 @@ __device__ __forceinline__ unsigned long long sq_step(int old, int d)
 // for 8 nodes at a time. Keeping the histogram atomics out of phase 1 matters: vector
 // memory counters drain in order, so an atomic issued between two gathers would make the
 // second wait for the atomic's round trip.
-__global__ __launch_bounds__(256) void k_fitness(Span sp)
+struct FitSums {
+    int c0 = -1;  // first of the lane's two columns; -1 when the lane has none
+    unsigned long long a0 = 0, a1 = 0, s0 = 0, s1 = 0;
+};
+
+__device__ __forceinline__ FitSums fitness_wave(const Item &it, int lb)
 {
-    int lb, nblk;
-    const Item &it = sp.items[item_of(sp, lb, nblk)];
+    FitSums out;
     const GGraph g = gview(it.g);
     const GLB int32_t *__restrict__ lab = glb(it.lab);
     const int32_t ld = it.fit_ld, pop = it.fit_pop, npw = it.fit_npw;
     const int nchunks = (pop + 127) / 128;
     GLB int32_t *__restrict__ D = glb(it.D);
-    GLB unsigned long long *__restrict__ A = glb(it.fit_A);
-    GLB unsigned long long *__restrict__ S = glb(it.fit_S);
     const int atomics_phase = it.hp.enabled ? 0 : 1;
     const int lane = lane_id();
-    const int wave = __builtin_amdgcn_readfirstlane(lb * 4 + (int)(threadIdx.x >> 6));
+    const int wave = __builtin_amdgcn_readfirstlane(lb * FIT_WAVES + (int)(threadIdx.x >> 6));
     const int chunk = wave % nchunks;
     const int32_t v0 = (int32_t)min((int64_t)(wave / nchunks) * npw, (int64_t)g.n);
-    if (v0 >= g.n) return;
+    if (v0 >= g.n) return out;
     const int32_t v1 = (int32_t)min((int64_t)v0 + npw, (int64_t)g.n);
     const int c0 = chunk * 128 + 2 * lane;
     const bool act1 = c0 + 1 < pop;
-    if (c0 >= pop) return;
+    if (c0 >= pop) return out;
     const GLB int32_t *__restrict__ lc = lab + c0;
 
     // phase 1: intra-community arcs
@@ -323,11 +326,44 @@ __global__ __launch_bounds__(256) void k_fitness(Span sp)
         }
     }
     // every intra edge {v,u} stands for the two intra arcs (v,u) and (u,v)
-    gatomic_add(A + c0, 2ull * (unsigned)cnt0);
-    if (act1) gatomic_add(A + c0 + 1, 2ull * (unsigned)cnt1);
-    if (atomics_phase) {
-        gatomic_add(S + c0, s0);
-        if (act1) gatomic_add(S + c0 + 1, s1);
+    out.c0 = c0;
+    out.a0 = 2ull * (unsigned)cnt0;
+    out.a1 = act1 ? 2ull * (unsigned)cnt1 : 0ull;
+    out.s0 = s0;
+    out.s1 = act1 ? s1 : 0ull;
+    return out;
+}
+
+// The waves' per-column sums are added up per workgroup in LDS first, so that A (and, on the
+// plain path, S) takes one global atomic per (workgroup, column) instead of one per (wave,
+// column): those atomics land on a few hundred addresses and execute at the memory side, one
+// after another per address, which on small graphs (many waves of a few nodes each) cost more
+// than the scan itself.
+__global__ __launch_bounds__(64 * FIT_WAVES) void k_fitness(Span sp)
+{
+    int lb, nblk;
+    const Item &it = sp.items[item_of(sp, lb, nblk)];
+    extern __shared__ unsigned long long fit_red[];  // [fit_ld] A, then [fit_ld] S (plain path)
+    const int ldf = it.fit_ld, pop = it.fit_pop;
+    const bool plain = !it.hp.enabled;
+    const int nred = plain ? 2 * ldf : ldf;
+    for (int i = threadIdx.x; i < nred; i += blockDim.x) fit_red[i] = 0ull;
+    __syncthreads();
+    const FitSums f = fitness_wave(it, lb);
+    if (f.c0 >= 0) {
+        atomicAdd(&fit_red[f.c0], f.a0);
+        atomicAdd(&fit_red[f.c0 + 1], f.a1);  // c0 + 1 < ld: ld is a multiple of 16
+        if (plain) {
+            atomicAdd(&fit_red[ldf + f.c0], f.s0);
+            atomicAdd(&fit_red[ldf + f.c0 + 1], f.s1);
+        }
+    }
+    __syncthreads();
+    GLB unsigned long long *__restrict__ A = glb(it.fit_A);
+    GLB unsigned long long *__restrict__ S = glb(it.fit_S);
+    for (int i = threadIdx.x; i < pop; i += blockDim.x) {
+        if (fit_red[i]) gatomic_add(A + i, fit_red[i]);
+        if (plain && fit_red[ldf + i]) gatomic_add(S + i, fit_red[ldf + i]);
     }
 }
 
@@ -345,6 +381,10 @@ __global__ __launch_bounds__(256) void k_fitness(Span sp)
 // ---------------------------------------------------------------------------------------
 // largest chunk of the binned histogram (nodes per k_bin workgroup)
 constexpr int BIN_MAX_NODES = 1024;
+// small graphs: narrower tiles (down to 2^12 labels) until pass 2 has this many (tile,
+// individual) workgroups, and chunks small enough that pass 2's threads each get one
+constexpr int HIST_MIN_WGS = 512;
+constexpr int HIST_MIN_CHUNKS = 256;
 
 HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, int32_t max_rbits)
 {
@@ -352,6 +392,7 @@ HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, in
     int rb = 0;
     const int rb_max = max_rbits < 10 ? 10 : (max_rbits > 14 ? 14 : max_rbits);
     while ((1 << rb) < n && rb < rb_max) ++rb;  // tiles of up to 16384 labels (64 KB of LDS)
+    while (rb > 12 && (((int64_t)n + (1 << rb) - 1) >> rb) * pop < HIST_MIN_WGS) --rb;
     p.rbits = rb;
     p.tiles = (int32_t)(((int64_t)n + (1 << rb) - 1) >> rb);
     const int counters = p.tiles * HB_CG;
@@ -359,6 +400,8 @@ HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, in
     int nb = (budget_words - counters - 1) / HB_CG;
     nb = nb / 64 * 64;
     if (nb > BIN_MAX_NODES) nb = BIN_MAX_NODES;
+    const int nb_par = (int)((n / HIST_MIN_CHUNKS) / 64 * 64);
+    if (nb > nb_par) nb = nb_par < 64 ? 64 : nb_par;
     p.nb = nb;
     // the plain histogram's n * pop global atomics are cheap for small problems, where the
     // two extra launches would cost more than they save
@@ -1595,7 +1638,7 @@ int32_t kind_blocks(Kind k, const Item &it)
     const DevGraph &g = it.g;
     switch (k) {
     case K_INIT: return ceil_div(g.n, NODE_BLOCK);
-    case K_FIT: return ceil_div((int64_t)ceil_div(g.n, it.fit_npw) * ((it.fit_pop + 127) / 128), 4);
+    case K_FIT: return ceil_div((int64_t)ceil_div(g.n, it.fit_npw) * ((it.fit_pop + 127) / 128), FIT_WAVES);
     case K_BIN: return it.hp.enabled ? it.hp.nchunks * it.hp.ngroups : 0;
     case K_HIST: return it.hp.enabled ? it.hp.tiles * it.fit_pop : 0;
     case K_CLEAR: {
@@ -1626,6 +1669,7 @@ int32_t kind_blocks(Kind k, const Item &it)
 size_t kind_lds(Kind k, const Item &it)
 {
     switch (k) {
+    case K_FIT: return sizeof(unsigned long long) * (size_t)it.fit_ld * (it.hp.enabled ? 1 : 2);
     case K_BIN:
         return it.hp.enabled ? sizeof(uint32_t) * ((size_t)it.hp.tiles * HB_CG + 1 +
                                                    (size_t)it.hp.nb * HB_CG + 4)
@@ -1654,7 +1698,7 @@ hipError_t launch_kind(Kind k, const Span &sp, int32_t blocks, size_t lds, int32
     const unsigned nb = (unsigned)blocks;
     switch (k) {
     case K_INIT: k_init<<<nb, 256, 0, s>>>(sp); break;
-    case K_FIT: k_fitness<<<nb, 256, 0, s>>>(sp); break;
+    case K_FIT: k_fitness<<<nb, 64 * FIT_WAVES, lds, s>>>(sp); break;
     case K_BIN: k_bin<<<nb, 256, lds, s>>>(sp); break;
     case K_HIST: k_hist<<<nb, 256, lds, s>>>(sp); break;
     case K_CLEAR: k_clear<<<nb, 256, 0, s>>>(sp); break;

@@ -15,7 +15,7 @@ int32_t round16(int32_t x);
 // Launch-shape knobs. Every value gives identical results; they only change how the work is
 // cut into workgroups (the autotuner picks them per batch).
 struct Tuning {
-    int32_t fit_target_waves = 16384;  // arc-scan waves wanted over the batch
+    int32_t fit_target_waves = 2048;   // arc-scan waves wanted over the batch
     int32_t xo_target_blocks = 2048;   // crossover/init workgroups wanted over the batch
     int32_t mut_target_items = 96;     // mutations queued per wave group (small degrees)
     int32_t hist_min_log2 = 20;        // binned histogram from 2^k (node, individual) pairs
