@@ -106,6 +106,7 @@ typedef struct {
     int32_t tune_mut_target_items;
     int32_t tune_hist_min_log2;
     int32_t tune_hist_rbits;
+    int32_t tune_hist_narrow;  /* 1: narrower histogram tiles and chunks on small graphs */
     double tune_probe_ms;      /* device time spent probing shapes (0 without autotuning) */
 } hpmocd_profile;
 

@@ -93,7 +93,10 @@ struct HistPlan {
     size_t entries = 0;    // uint32 entries of the run area
     size_t offsets = 0;    // uint32 offsets (per chunk and group: tiles * 16 + 1)
 };
-HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, int32_t max_rbits);
+// narrow: on small graphs, narrower tiles and smaller chunks so that pass 2 alone fills the
+// device
+HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, int32_t max_rbits,
+                   bool narrow);
 
 // One population on one graph, as the kernels see it (lives in device memory). A run is a
 // batch of one item; the batched form puts many graphs, each with its own population, into

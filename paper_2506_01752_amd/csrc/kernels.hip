@@ -386,13 +386,14 @@ constexpr int BIN_MAX_NODES = 1024;
 constexpr int HIST_MIN_WGS = 512;
 constexpr int HIST_MIN_CHUNKS = 256;
 
-HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, int32_t max_rbits)
+HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, int32_t max_rbits,
+                   bool narrow)
 {
     HistPlan p;
     int rb = 0;
     const int rb_max = max_rbits < 10 ? 10 : (max_rbits > 14 ? 14 : max_rbits);
     while ((1 << rb) < n && rb < rb_max) ++rb;  // tiles of up to 16384 labels (64 KB of LDS)
-    while (rb > 12 && (((int64_t)n + (1 << rb) - 1) >> rb) * pop < HIST_MIN_WGS) --rb;
+    while (narrow && rb > 12 && (((int64_t)n + (1 << rb) - 1) >> rb) * pop < HIST_MIN_WGS) --rb;
     p.rbits = rb;
     p.tiles = (int32_t)(((int64_t)n + (1 << rb) - 1) >> rb);
     const int counters = p.tiles * HB_CG;
@@ -401,7 +402,7 @@ HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, in
     nb = nb / 64 * 64;
     if (nb > BIN_MAX_NODES) nb = BIN_MAX_NODES;
     const int nb_par = (int)((n / HIST_MIN_CHUNKS) / 64 * 64);
-    if (nb > nb_par) nb = nb_par < 64 ? 64 : nb_par;
+    if (narrow && nb > nb_par) nb = nb_par < 64 ? 64 : nb_par;
     p.nb = nb;
     // the plain histogram's n * pop global atomics are cheap for small problems, where the
     // two extra launches would cost more than they save

@@ -40,7 +40,7 @@ RunLayout carve_run(void *ws, int32_t n, int32_t pop, int32_t es, int32_t max_de
                     const Tuning &t, bool both_histograms)
 {
     RunLayout L;
-    L.hp = hist_plan(n, pop, max_deg, t.hist_min_log2, t.hist_rbits);
+    L.hp = hist_plan(n, pop, max_deg, t.hist_min_log2, t.hist_rbits, t.hist_narrow != 0);
     L.ld = round16(pop);
     L.plane = (size_t)n * (size_t)L.ld * sizeof(int32_t);
     Carver cv(ws);
@@ -52,12 +52,13 @@ RunLayout carve_run(void *ws, int32_t n, int32_t pop, int32_t es, int32_t max_de
     L.C = cv.take<int32_t>(cells);
     size_t entries = L.hp.enabled ? L.hp.entries : 0, offsets = L.hp.enabled ? L.hp.offsets : 0;
     if (both_histograms)
-        for (int32_t rb : HIST_RBITS_CHOICES) {  // every binned plan the autotuner may pick
-            const HistPlan h = hist_plan(n, pop, max_deg, 0, rb);
-            if (!h.enabled) continue;
-            entries = std::max(entries, h.entries);
-            offsets = std::max(offsets, h.offsets);
-        }
+        for (int32_t rb : HIST_RBITS_CHOICES)  // every binned plan the autotuner may pick
+            for (bool narrow : {false, true}) {
+                const HistPlan h = hist_plan(n, pop, max_deg, 0, rb, narrow);
+                if (!h.enabled) continue;
+                entries = std::max(entries, h.entries);
+                offsets = std::max(offsets, h.offsets);
+            }
     if (entries) {
         L.run = cv.take<uint32_t>(entries);
         L.off = cv.take<uint32_t>(offsets);
@@ -569,15 +570,17 @@ static int autotune(const hpmocd_graph *const *graphs, int32_t count, const hpmo
     const int32_t xo_c[] = {512, 2048, 8192};
     const int32_t mut_c[] = {48, 96, 192};
     const int32_t hist_c[] = {16, 20, 24, 31};
-    for (int knob = 0; knob < 5; ++knob) {
+    const int32_t narrow_c[] = {0, 1};
+    for (int knob = 0; knob < 6; ++knob) {
         const int32_t *vals = knob == 0 ? fit_c : knob == 1 ? xo_c : knob == 2 ? mut_c
-                              : knob == 3 ? hist_c : HIST_RBITS_CHOICES;
-        const int nv = knob == 0 || knob == 3 ? 4 : 3;
+                              : knob == 3 ? hist_c : knob == 4 ? HIST_RBITS_CHOICES : narrow_c;
+        const int nv = knob == 0 || knob == 3 ? 4 : (knob == 5 ? 2 : 3);
         for (int i = 0; i < nv; ++i) {
             Tuning t = cur;
             int32_t *field = knob == 0 ? &t.fit_target_waves : knob == 1 ? &t.xo_target_blocks
                              : knob == 2 ? &t.mut_target_items
-                             : knob == 3 ? &t.hist_min_log2 : &t.hist_rbits;
+                             : knob == 3 ? &t.hist_min_log2
+                             : knob == 4 ? &t.hist_rbits : &t.hist_narrow;
             if (*field == vals[i]) continue;
             *field = vals[i];
             double ms = 0;
@@ -608,7 +611,7 @@ int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_par
     DrainOnExit drain{s};
     const int32_t T = params[0].generations;
     const bool autotune_on = (flags & HPMOCD_AUTOTUNE) != 0;
-    Tuning t;
+    Tuning t = default_tuning(count);
     double probe_ms = 0;
     if (autotune_on && (rc = autotune(graphs, count, params, ws, ws_bytes, s, &t, &probe_ms)))
         return rc;
@@ -697,6 +700,7 @@ int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_par
         prof->tune_mut_target_items = B.tuning.mut_target_items;
         prof->tune_hist_min_log2 = B.tuning.hist_min_log2;
         prof->tune_hist_rbits = B.tuning.hist_rbits;
+        prof->tune_hist_narrow = B.tuning.hist_narrow;
         prof->tune_probe_ms = probe_ms;
     }
     return HPMOCD_OK;
@@ -705,8 +709,14 @@ int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_par
 size_t batch_workspace(const hpmocd_graph *const *graphs, int32_t count,
                        const hpmocd_params *params, bool both)
 {
+    return batch_layout(graphs, count, params, default_tuning(count), both).bytes;
+}
+
+Tuning default_tuning(int32_t count)
+{
     Tuning t;
-    return batch_layout(graphs, count, params, t, both).bytes;
+    t.hist_narrow = count > 1 ? 0 : 1;
+    return t;
 }
 
 }  // namespace hpm
@@ -887,7 +897,9 @@ int hpmocd_eval_workspace_size(const hpmocd_graph *g, int32_t n_ind, size_t *byt
 {
     if (!g || !bytes || n_ind < 1) return HPMOCD_ERR_ARG;
     const int32_t ld = round16(n_ind);
-    const HistPlan hp = hist_plan(g->n, n_ind, g->max_deg, Tuning{}.hist_min_log2, Tuning{}.hist_rbits);
+    const Tuning t;
+    const HistPlan hp = hist_plan(g->n, n_ind, g->max_deg, t.hist_min_log2, t.hist_rbits,
+                                  t.hist_narrow != 0);
     size_t b = align_up((size_t)g->n * ld * 4);  // transposed labels
     b += hp.enabled ? align_up(hp.entries * 4) + align_up(hp.offsets * 4) : align_up((size_t)g->n * ld * 4);
     b += 2 * align_up(8 * (size_t)n_ind) + 2 * align_up(8 * (size_t)n_ind);
@@ -916,7 +928,9 @@ int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, v
     p += align_up(plane);
     Item it{};
     it.g = dev_graph(G);
-    it.hp = hist_plan(G->n, n_ind, G->max_deg, Tuning{}.hist_min_log2, Tuning{}.hist_rbits);
+    const Tuning tdef;
+    it.hp = hist_plan(G->n, n_ind, G->max_deg, tdef.hist_min_log2, tdef.hist_rbits,
+                      tdef.hist_narrow != 0);
     if (it.hp.enabled) {
         it.run = (uint32_t *)p;
         p += align_up(it.hp.entries * 4);

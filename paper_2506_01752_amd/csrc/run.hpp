@@ -20,7 +20,13 @@ struct Tuning {
     int32_t mut_target_items = 96;     // mutations queued per wave group (small degrees)
     int32_t hist_min_log2 = 20;        // binned histogram from 2^k (node, individual) pairs
     int32_t hist_rbits = 14;           // binned histogram tiles of up to 2^k labels
+    int32_t hist_narrow = 1;           // small graphs: narrower tiles, smaller chunks
 };
+
+// Default shapes for a batch of `count` populations. A lone small graph needs narrower
+// histogram tiles and smaller chunks to occupy the device; in a batch the populations fill it
+// together, and the extra workgroups and offsets only cost.
+Tuning default_tuning(int32_t count);
 
 // tile sizes (log2 labels per tile) the autotuner tries for the binned histogram
 constexpr int32_t HIST_RBITS_CHOICES[3] = {12, 13, 14};
