@@ -438,9 +438,15 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *w
     return base + x - v;
 }
 
-constexpr int BIN_UNROLL = 32;
+// A k_bin workgroup holds its whole chunk (at most BIN_MAX_NODES x 16 items), BIN_IPT items
+// per thread in registers, so that both passes use one read of the labels. The launch takes
+// as many threads as its largest chunk has nodes (rounded up to whole waves, at most
+// BIN_THREADS): small graphs' 64-node chunks get one-wave workgroups.
+constexpr int BIN_THREADS = 1024;
+constexpr int BIN_IPT = BIN_MAX_NODES * HB_CG / BIN_THREADS;
+static_assert(BIN_IPT == HB_CG, "a chunk of nb nodes needs nb threads");
 
-__global__ __launch_bounds__(256) void k_bin(Span sp)
+__global__ __launch_bounds__(BIN_THREADS) void k_bin(Span sp)
 {
     int lb, nblk;
     const Item &it = sp.items[item_of(sp, lb, nblk)];
@@ -454,7 +460,7 @@ __global__ __launch_bounds__(256) void k_bin(Span sp)
     const int counters = p.tiles * HB_CG;
     uint32_t *cnt = bl;                             // [counters + 1]
     uint32_t *stage = bl + counters + 1;            // [nb * 16]
-    uint32_t *wsum = stage + (size_t)p.nb * HB_CG;  // [4]
+    uint32_t *wsum = stage + (size_t)p.nb * HB_CG;  // [BIN_THREADS / 64]
     // the groups of one chunk read the same label rows (16 columns each): run them together
     const int lg = xcd_remap(lb, nblk);
     const int chunk = lg / p.ngroups, grp = lg % p.ngroups;
@@ -465,22 +471,20 @@ __global__ __launch_bounds__(256) void k_bin(Span sp)
     const uint32_t rmask = (1u << p.rbits) - 1u;
     for (int i = threadIdx.x; i <= counters; i += blockDim.x) cnt[i] = 0;
     __syncthreads();
-    // items it = 16 * (v - v0) + jl: a wave reads four 64-byte row segments
-    const int items = nv * HB_CG;
-    for (int base = 0; base < items; base += (int)blockDim.x * BIN_UNROLL) {
-        uint32_t x[BIN_UNROLL];
-        bool ok[BIN_UNROLL];
+    // items itm = 16 * (v - v0) + jl: a wave reads four 64-byte row segments
+    const int items = nv * HB_CG;  // <= blockDim.x * BIN_IPT (blockDim.x >= nb)
+    uint32_t x[BIN_IPT];
+    bool ok[BIN_IPT];
 #pragma unroll
-        for (int k = 0; k < BIN_UNROLL; ++k) {
-            const int itm = base + k * (int)blockDim.x + (int)threadIdx.x;
-            ok[k] = itm < items && (itm & (HB_CG - 1)) < cg;
-            x[k] = ok[k] ? (uint32_t)lab[(size_t)(v0 + (itm >> 4)) * ld + j0 + (itm & (HB_CG - 1))] : 0u;
-        }
+    for (int k = 0; k < BIN_IPT; ++k) {
+        const int itm = k * (int)blockDim.x + (int)threadIdx.x;
+        ok[k] = itm < items && (itm & (HB_CG - 1)) < cg;
+        x[k] = ok[k] ? (uint32_t)lab[(size_t)(v0 + (itm >> 4)) * ld + j0 + (itm & (HB_CG - 1))] : 0u;
+    }
 #pragma unroll
-        for (int k = 0; k < BIN_UNROLL; ++k) {
-            const int itm = base + k * (int)blockDim.x + (int)threadIdx.x;
-            if (ok[k]) atomicAdd(&cnt[(x[k] >> p.rbits) * HB_CG + (itm & (HB_CG - 1))], 1u);
-        }
+    for (int k = 0; k < BIN_IPT; ++k) {
+        const int itm = k * (int)blockDim.x + (int)threadIdx.x;
+        if (ok[k]) atomicAdd(&cnt[(x[k] >> p.rbits) * HB_CG + (itm & (HB_CG - 1))], 1u);
     }
     __syncthreads();
     // exclusive scan of the counters: each thread scans a contiguous slice
@@ -501,24 +505,19 @@ __global__ __launch_bounds__(256) void k_bin(Span sp)
     GLB uint32_t *o = off + ((size_t)chunk * p.ngroups + grp) * (size_t)(counters + 1);
     for (int i = threadIdx.x; i <= counters; i += blockDim.x) o[i] = cnt[i];
     __syncthreads();
-    for (int base = 0; base < items; base += (int)blockDim.x * BIN_UNROLL) {
-        uint32_t x[BIN_UNROLL], d[BIN_UNROLL];
-        bool ok[BIN_UNROLL];
+    uint32_t d[BIN_IPT];
 #pragma unroll
-        for (int k = 0; k < BIN_UNROLL; ++k) {
-            const int itm = base + k * (int)blockDim.x + (int)threadIdx.x;
-            ok[k] = itm < items && (itm & (HB_CG - 1)) < cg;
-            const int32_t v = v0 + (ok[k] ? (itm >> 4) : 0);
-            x[k] = ok[k] ? (uint32_t)lab[(size_t)v * ld + j0 + (itm & (HB_CG - 1))] : 0u;
-            d[k] = (uint32_t)(g.row_ptr[v + 1] - g.row_ptr[v]);
-        }
+    for (int k = 0; k < BIN_IPT; ++k) {
+        const int itm = k * (int)blockDim.x + (int)threadIdx.x;
+        const int32_t v = v0 + (ok[k] ? (itm >> 4) : 0);
+        d[k] = (uint32_t)(g.row_ptr[v + 1] - g.row_ptr[v]);
+    }
 #pragma unroll
-        for (int k = 0; k < BIN_UNROLL; ++k) {
-            const int itm = base + k * (int)blockDim.x + (int)threadIdx.x;
-            if (ok[k]) {
-                const uint32_t pos = atomicAdd(&cnt[(x[k] >> p.rbits) * HB_CG + (itm & (HB_CG - 1))], 1u);
-                stage[pos] = (x[k] & rmask) | (d[k] << p.rbits);
-            }
+    for (int k = 0; k < BIN_IPT; ++k) {
+        const int itm = k * (int)blockDim.x + (int)threadIdx.x;
+        if (ok[k]) {
+            const uint32_t pos = atomicAdd(&cnt[(x[k] >> p.rbits) * HB_CG + (itm & (HB_CG - 1))], 1u);
+            stage[pos] = (x[k] & rmask) | (d[k] << p.rbits);
         }
     }
     __syncthreads();
@@ -1673,7 +1672,7 @@ size_t kind_lds(Kind k, const Item &it)
     case K_FIT: return sizeof(unsigned long long) * (size_t)it.fit_ld * (it.hp.enabled ? 1 : 2);
     case K_BIN:
         return it.hp.enabled ? sizeof(uint32_t) * ((size_t)it.hp.tiles * HB_CG + 1 +
-                                                   (size_t)it.hp.nb * HB_CG + 4)
+                                                   (size_t)it.hp.nb * HB_CG + BIN_THREADS / 64)
                              : 0;
     case K_HIST: return it.hp.enabled ? sizeof(uint32_t) * ((size_t)1 << it.hp.rbits) : 0;
     case K_XO:
@@ -1688,6 +1687,7 @@ size_t kind_lds(Kind k, const Item &it)
 int32_t kind_aux(Kind k, const Item &it)
 {
     if (k == K_XO) return it.c.es;
+    if (k == K_BIN) return it.hp.enabled ? (it.hp.nb + 63) / 64 * 64 : 0;  // threads
     if (k == K_MUTL) return large_pmax(it);
     return 0;
 }
@@ -1700,7 +1700,11 @@ hipError_t launch_kind(Kind k, const Span &sp, int32_t blocks, size_t lds, int32
     switch (k) {
     case K_INIT: k_init<<<nb, 256, 0, s>>>(sp); break;
     case K_FIT: k_fitness<<<nb, 64 * FIT_WAVES, lds, s>>>(sp); break;
-    case K_BIN: k_bin<<<nb, 256, lds, s>>>(sp); break;
+    case K_BIN: {
+        const unsigned threads = (unsigned)(aux < 64 ? 64 : (aux > BIN_THREADS ? BIN_THREADS : aux));
+        k_bin<<<nb, threads, lds, s>>>(sp);
+        break;
+    }
     case K_HIST: k_hist<<<nb, 256, lds, s>>>(sp); break;
     case K_CLEAR: k_clear<<<nb, 256, 0, s>>>(sp); break;
     case K_XO:
