@@ -126,10 +126,12 @@ void Pop::shape(const Tuning &t, int64_t batch_nodes)
     const int64_t npw = batch_nodes / std::max<int64_t>(1, t.fit_target_waves);
     fit_npw = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, npw));
     const int64_t nb = batch_nodes / std::max<int64_t>(1, t.xo_target_blocks);
-    // the crossover stages its nodes' two rows in LDS beside its tables: 64 KB in all
+    // the crossover stages its nodes' two rows in LDS beside its tables: 64 KB in all, and
+    // at most 16 nodes per workgroup (measured at |V| = 1M: 8, 16, 24, 32, 64 nodes ->
+    // 0.62, 0.56, 0.57, 0.58, 0.82 ms of crossover per generation)
     const int64_t tables = 4 * ((((int64_t)2 + p.parents_per_child) * p.pop_size + 3) & ~3);
     const int64_t lds_nodes = std::max<int64_t>(1, (65536 - tables) / (8 * (int64_t)L.ld));
-    xo_nb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(32, lds_nodes), nb));
+    xo_nb = (int32_t)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(16, lds_nodes), nb));
 }
 
 Item Pop::item(int which) const
