@@ -552,7 +552,7 @@ def main():
                              "gens_per_s": T * args.steps / (sum(loops) / 1e3)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, kw["seed"])
-        # host cores: the GPU machine grants 16 to a job whatever the machine shows
+        # at most 16 host threads: a job's CPU share on a one-GPU host, whatever the core count shows
         out["cpu_oracle_generation"] = cpu_generation(g, kw, min(16, os.cpu_count() or 1))
     print(json.dumps(out), flush=True)
 
