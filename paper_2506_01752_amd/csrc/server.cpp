@@ -381,6 +381,8 @@ int hpmocd_server_create(const hpmocd_server_config *cfg, void *d_arena, size_t 
     hpmocd_server *s = new (std::nothrow) hpmocd_server;
     if (!s) return HPMOCD_ERR_NOMEM;
     s->cfg = *cfg;
+    // resident requests share every launch, like a batch (FIFO runs go through run_batch alone)
+    s->tuning = default_tuning(cfg->max_active);
     s->arena = (char *)d_arena;
     s->table_bytes = over;
     s->stream = (hipStream_t)stream;
