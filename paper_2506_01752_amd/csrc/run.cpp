@@ -91,6 +91,12 @@ RunLayout carve_run(void *ws, int32_t n, int32_t pop, int32_t es, int32_t max_de
     return L;
 }
 
+int32_t mut_target_for(const Tuning &t, int64_t nodes)
+{
+    if (t.mut_target_items > 0) return t.mut_target_items;
+    return nodes >= (int64_t(1) << 18) ? 96 : 48;  // measured best at 1M and at 1k-40k nodes
+}
+
 GaConst ga_const(const hpmocd_params *p, int32_t ld, int32_t mut_target)
 {
     GaConst c;
@@ -115,7 +121,7 @@ void Pop::setup(const hpmocd_graph *graph, const hpmocd_params &params, void *ws
     G = graph;
     p = params;
     L = carve_run(ws, G->n, p.pop_size, p.parents_per_child, G->max_deg, t, both_histograms);
-    c = ga_const(&p, L.ld, t.mut_target_items);
+    c = ga_const(&p, L.ld, mut_target_for(t, std::max<int64_t>(batch_nodes, G->n)));
     dg = dev_graph(G);
     shape(t, batch_nodes);
     cur = 0;
@@ -614,6 +620,9 @@ int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_par
     const int32_t T = params[0].generations;
     const bool autotune_on = (flags & HPMOCD_AUTOTUNE) != 0;
     Tuning t = default_tuning(count);
+    int64_t nodes = 0;
+    for (int32_t i = 0; i < count; ++i) nodes += graphs[i]->n;
+    t.mut_target_items = mut_target_for(t, nodes);  // explicit, so the profile reports it
     double probe_ms = 0;
     if (autotune_on && (rc = autotune(graphs, count, params, ws, ws_bytes, s, &t, &probe_ms)))
         return rc;

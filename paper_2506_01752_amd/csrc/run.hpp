@@ -17,7 +17,8 @@ int32_t round16(int32_t x);
 struct Tuning {
     int32_t fit_target_waves = 2048;   // arc-scan waves wanted over the batch
     int32_t xo_target_blocks = 2048;   // crossover/init workgroups wanted over the batch
-    int32_t mut_target_items = 96;     // mutations queued per wave group (small degrees)
+    int32_t mut_target_items = 0;      // mutations queued per wave group (small degrees);
+                                       // 0: by size (96 from 2^18 nodes, else 48)
     int32_t hist_min_log2 = 20;        // binned histogram from 2^k (node, individual) pairs
     int32_t hist_rbits = 14;           // binned histogram tiles of up to 2^k labels
     int32_t hist_narrow = 1;           // small graphs: narrower tiles, smaller chunks
@@ -27,6 +28,8 @@ struct Tuning {
 // histogram tiles and smaller chunks to occupy the device; in a batch the populations fill it
 // together, and the extra workgroups and offsets only cost.
 Tuning default_tuning(int32_t count);
+// the mutation queue target a tuning resolves to for a launch over `nodes` nodes
+int32_t mut_target_for(const Tuning &t, int64_t nodes);
 
 // tile sizes (log2 labels per tile) the autotuner tries for the binned histogram
 constexpr int32_t HIST_RBITS_CHOICES[3] = {12, 13, 14};
