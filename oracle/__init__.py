@@ -74,6 +74,14 @@ def _L():
         lib.or_neighbour_plurality.restype = C.c_int32
         lib.or_mutate.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_double, C.c_uint64,
                                   C.c_uint32, C.c_uint32, i32p]
+        lib.or_tournament.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                      C.c_int32]
+        lib.or_tournament.restype = C.c_int32
+        lib.or_gate.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_double, C.c_int32]
+        lib.or_gate.restype = C.c_int32
+        lib.or_offspring.argtypes = [C.c_int32, i32p, i32p, i32p, C.c_int32, C.c_int32,
+                                     C.c_double, C.c_double, C.c_uint64, C.c_uint32,
+                                     C.c_uint32, i32p, i32p, i32p]
         lib.or_rank.argtypes = [C.c_int32, i64p, i64p, i32p]
         lib.or_crowding.argtypes = [C.c_int32, i32p, i64p, i64p, f64p, f64p, f64p]
         lib.or_order.argtypes = [C.c_int32, i32p, f64p, i32p]
@@ -159,6 +167,33 @@ def mutate(row_ptr, col, child, mutation_p: float, seed: int, gen: int, j: int) 
     _L().or_mutate(len(rp) - 1, _p(rp, C.c_int32), _p(cl, C.c_int32), _p(ch, C.c_int32),
                    mutation_p, seed, gen, j, _p(out, C.c_int32))
     return out
+
+
+def tournament(seed: int, gen: int, j: int, k: int, pop_size: int) -> int:
+    """Winner position of parent slot k of offspring j (Alg. 1 TournamentSelection, k = 2)
+    in a population already in crowded-comparison order."""
+    return int(_L().or_tournament(seed, gen, j, k, pop_size))
+
+
+def gate(seed: int, gen: int, j: int, crossover_p: float, parents_per_child: int) -> int:
+    """Crossover gate of offspring j (Alg. 2): -1 = ensemble crossover, else the copied
+    parent slot."""
+    return int(_L().or_gate(seed, gen, j, crossover_p, parents_per_child))
+
+
+def offspring(row_ptr, col, pop, parents_per_child: int, crossover_p: float,
+              mutation_p: float, seed: int, gen: int, j: int):
+    """Offspring j of generation gen from the rows of ``pop`` (N_p x n, crowded order):
+    tournaments, gate, crossover, mutation. Returns (child, parent positions, gate)."""
+    rp, cl, P = _i32(row_ptr), _i32(col), _i32(pop)
+    np_, n = P.shape
+    child = np.empty(n, dtype=np.int32)
+    pos = np.empty(parents_per_child, dtype=np.int32)
+    g = C.c_int32()
+    _L().or_offspring(n, _p(rp, C.c_int32), _p(cl, C.c_int32), _p(P, C.c_int32), np_,
+                      parents_per_child, crossover_p, mutation_p, seed, gen, j,
+                      _p(child, C.c_int32), _p(pos, C.c_int32), C.byref(g))
+    return child, pos, g.value
 
 
 def rank(k1, k2) -> np.ndarray:

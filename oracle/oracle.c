@@ -238,6 +238,37 @@ void or_init_individual(int32_t n, const int32_t *row_ptr, const int32_t *col, u
 }
 
 /* ------------------------------------------------------------------------------------ */
+/* Tournament selection (Alg. 1 TournamentSelection, size k = 2) for parent slot k of     */
+/* offspring j at generation g. The population is already in crowded-comparison order     */
+/* (rank ascending, crowding descending, position ascending), so of two contestants the   */
+/* one at the lower position is the better one (equal positions: the same member). The   */
+/* contestants are drawn independently and with replacement from the SEL draw of counter  */
+/* (k, j, g). Returns the winner's position in [0, np).                                   */
+/* ------------------------------------------------------------------------------------ */
+int32_t or_tournament(uint64_t seed, uint32_t gen, uint32_t j, uint32_t k, int32_t np)
+{
+    uint32_t w[4];
+    or_philox(seed, k, j, gen, OR_TAG_SEL, w);
+    uint32_t a = or_pick(w[0], (uint32_t)np), b = or_pick(w[1], (uint32_t)np);
+    return (int32_t)(a < b ? a : b);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Crossover gate (section 4.3.1, Alg. 2): a uniform x is drawn and the ensemble crossover */
+/* happens when x <= C_P, i.e. with probability C_P; otherwise the child is a copy of one  */
+/* of its E_S parents, chosen uniformly. x is the first word of the SEL draw of counter    */
+/* (0xFFFFFFFF, j, g), read as the integer event w0 < floor(C_P 2^32); the second word      */
+/* picks the copied parent. Returns -1 for crossover, else the copied parent slot.         */
+/* ------------------------------------------------------------------------------------ */
+int32_t or_gate(uint64_t seed, uint32_t gen, uint32_t j, double crossover_p, int32_t es)
+{
+    uint32_t w[4];
+    or_philox(seed, OR_GATE_X, j, gen, OR_TAG_SEL, w);
+    if ((uint64_t)w[0] < or_thr(crossover_p)) return -1;
+    return (int32_t)or_pick(w[1], (uint32_t)es);
+}
+
+/* ------------------------------------------------------------------------------------ */
 /* Crossover (section 4.3.1, Alg. 2) of offspring j at generation g from E_S parent rows.  */
 /* gate_copy < 0: majority vote per node; gate_copy = k: copy of parent k.                 */
 /* ------------------------------------------------------------------------------------ */
@@ -312,6 +343,52 @@ void or_mutate(int32_t n, const int32_t *row_ptr, const int32_t *col, const int3
     int32_t *scratch = (int32_t *)malloc(sizeof(int32_t) * (size_t)maxd);
     mutate(&g, C, or_thr(mutation_p), seed, gen, j, out, scratch);
     free(scratch);
+    graph_free(&g);
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* One offspring (Alg. 1 steps inside a generation): E_S tournaments over the population   */
+/* P in crowded order (rows P[0..np)), the crossover gate, the crossover and the mutation. */
+/* Writes the child to out and, when parent_pos is not NULL, the E_S winners' positions    */
+/* and the gate's result.                                                                 */
+/* ------------------------------------------------------------------------------------ */
+static void offspring(const or_graph *g, const int32_t *const *P, int32_t np, int32_t es,
+                      double crossover_p, uint64_t thr_m, uint64_t seed, uint32_t gen,
+                      uint32_t j, int32_t *C, int32_t *scratch, int32_t *out,
+                      int32_t *parent_pos, int32_t *gate_out)
+{
+    const int32_t *par[8];
+    for (int32_t k = 0; k < es; ++k) {
+        int32_t q = or_tournament(seed, gen, j, (uint32_t)k, np);
+        par[k] = P[q];
+        if (parent_pos) parent_pos[k] = q;
+    }
+    int32_t gate_copy = or_gate(seed, gen, j, crossover_p, es);
+    if (gate_out) *gate_out = gate_copy;
+    crossover(g->n, es, par, gate_copy, seed, gen, j, C);
+    mutate(g, C, thr_m, seed, gen, j, out, scratch);
+}
+
+/* offspring j of generation gen from the population rows `pop` (np x n, crowded order) */
+void or_offspring(int32_t n, const int32_t *row_ptr, const int32_t *col, const int32_t *pop,
+                  int32_t np, int32_t es, double crossover_p, double mutation_p, uint64_t seed,
+                  uint32_t gen, uint32_t j, int32_t *child, int32_t *parent_pos,
+                  int32_t *gate_out)
+{
+    or_graph g;
+    graph_copy(&g, n, row_ptr, col);
+    int32_t maxd = 1;
+    for (int32_t v = 0; v < n; ++v)
+        if (row_ptr[v + 1] - row_ptr[v] > maxd) maxd = row_ptr[v + 1] - row_ptr[v];
+    const int32_t **rows = (const int32_t **)malloc(sizeof(int32_t *) * (size_t)np);
+    for (int32_t q = 0; q < np; ++q) rows[q] = pop + (size_t)q * (size_t)n;
+    int32_t *scratch = (int32_t *)malloc(sizeof(int32_t) * (size_t)maxd);
+    int32_t *C = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    offspring(&g, rows, np, es, crossover_p, or_thr(mutation_p), seed, gen, j, C, scratch,
+              child, parent_pos, gate_out);
+    free(C);
+    free(scratch);
+    free(rows);
     graph_free(&g);
 }
 
@@ -523,8 +600,7 @@ int or_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const or_param
     if (row_ptr[n] <= 0) return -1;
     or_graph G;
     graph_copy(&G, n, row_ptr, col);
-    const uint64_t seed = prm->seed, thr_c = or_thr(prm->crossover_p),
-                   thr_m = or_thr(prm->mutation_p);
+    const uint64_t seed = prm->seed, thr_m = or_thr(prm->mutation_p);
     int32_t maxd = 1;
     for (int32_t v = 0; v < n; ++v)
         if (G.row_ptr[v + 1] - G.row_ptr[v] > maxd) maxd = G.row_ptr[v + 1] - G.row_ptr[v];
@@ -534,6 +610,7 @@ int or_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const or_param
         store[i].row = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     const member **P = (const member **)malloc(sizeof(member *) * (size_t)np);
     const member **R = (const member **)malloc(sizeof(member *) * (size_t)(2 * np));
+    const int32_t **Prow = (const int32_t **)malloc(sizeof(int32_t *) * (size_t)np);
     member **freeq = (member **)malloc(sizeof(member *) * (size_t)np);
     int64_t *Dall = (int64_t *)malloc(sizeof(int64_t) * (size_t)n * (size_t)threads);
     int32_t *scall = (int32_t *)malloc(sizeof(int32_t) * (size_t)maxd * (size_t)threads);
@@ -578,6 +655,8 @@ int or_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const or_param
         free(tmp);
         free(order);
 
+        for (int32_t q = 0; q < np; ++q) Prow[q] = P[q]->row;
+
         /* the storage slots not holding a member of P receive the offspring */
         int32_t nfree = 0;
         for (int32_t i = 0; i < 2 * np; ++i) {
@@ -594,18 +673,9 @@ int or_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const or_param
             int32_t *C = Call + (size_t)t * (size_t)n;
             int32_t *scratch = scall + (size_t)t * (size_t)maxd;
             int64_t *D = Dall + (size_t)t * (size_t)n;
-            const int32_t *par[8];
-            uint32_t w[4];
-            for (int32_t k = 0; k < es; ++k) {
-                or_philox(seed, (uint32_t)k, (uint32_t)j, (uint32_t)gen, OR_TAG_SEL, w);
-                uint32_t a = or_pick(w[0], (uint32_t)np), b = or_pick(w[1], (uint32_t)np);
-                par[k] = P[a < b ? a : b]->row; /* lower position wins the crowded comparison */
-            }
-            or_philox(seed, OR_GATE_X, (uint32_t)j, (uint32_t)gen, OR_TAG_SEL, w);
-            int32_t gate_copy = ((uint64_t)w[0] < thr_c) ? -1 : (int32_t)or_pick(w[1], (uint32_t)es);
-            crossover(n, es, par, gate_copy, seed, (uint32_t)gen, (uint32_t)j, C);
             member *q = freeq[j];
-            mutate(&G, C, thr_m, seed, (uint32_t)gen, (uint32_t)j, q->row, scratch);
+            offspring(&G, Prow, np, es, prm->crossover_p, thr_m, seed, (uint32_t)gen,
+                      (uint32_t)j, C, scratch, q->row, NULL, NULL);
             eval_graph(&G, q->row, D, &q->A, &q->S, &q->f1, &q->f2);
         }
 
@@ -646,6 +716,7 @@ int or_run(int32_t n, const int32_t *row_ptr, const int32_t *col, const or_param
     free(store);
     free(P);
     free(R);
+    free(Prow);
     free(freeq);
     free(Dall);
     free(scall);

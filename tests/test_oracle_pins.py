@@ -390,3 +390,137 @@ def test_run_edge_cases(oracle_lib):
     deg = np.diff(gi.row_ptr)
     for row in fr.labels:     # isolated nodes are never mutated: they keep their init label
         assert (row[deg == 0] == np.flatnonzero(deg == 0)).all()
+
+
+# ------------------------------------------------------------------------------------------
+# tournament selection (Alg. 1 TournamentSelection, k = 2) and the crossover gate (Alg. 2,
+# section 4.3.1)
+# ------------------------------------------------------------------------------------------
+def _chi2(cnt, p):
+    e = p * cnt.sum()
+    return float(((cnt - e) ** 2 / e).sum())
+
+
+@pytest.mark.parametrize("N,crit", [(2, 10.83), (7, 22.46), (100, 148.2), (130, 184.4)])
+def test_tournament_winner_law(oracle_lib, N, crit):
+    """A binary tournament with replacement over a population in crowded order, the better
+    (lower) position winning, picks position q with probability ((N-q)^2 - (N-q-1)^2) / N^2
+    = (2(N-q) - 1) / N^2. The reversed rule (higher position wins) has law (2q + 1) / N^2 and
+    a single uniform contestant 1 / N; both must fail the same chi-square test (p = 0.001)."""
+    draws = 60 * N if N > 10 else 20000
+    cnt = np.zeros(N, dtype=np.int64)
+    for t in range(draws):
+        g, j, k = 1 + t % 97, t // 97, t % 5
+        q = oracle_lib.tournament(seed=11, gen=g, j=j, k=k, pop_size=N)
+        assert 0 <= q < N
+        cnt[q] += 1
+    q = np.arange(N)
+    law = (2 * (N - q) - 1) / N**2
+    assert abs(law.sum() - 1) < 1e-12
+    assert _chi2(cnt, law) < crit
+    assert _chi2(cnt, (2 * q + 1) / N**2) > 10 * crit        # higher position winning
+    assert _chi2(cnt, np.full(N, 1.0 / N)) > 2 * crit         # no comparison at all
+
+
+def test_tournament_edges_and_slot_independence(oracle_lib):
+    assert all(oracle_lib.tournament(3, g, j, k, 1) == 0
+               for g in range(3) for j in range(5) for k in range(8))
+    # the E_S slots of one offspring are independent tournaments: the joint law of slot 0
+    # and slot 1 winning in the top half factorises (2 x 2 contingency chi-square, 1 dof)
+    N, tab = 50, np.zeros((2, 2), dtype=np.int64)
+    for j in range(8000):
+        a = oracle_lib.tournament(5, 3, j, 0, N) < N // 2
+        b = oracle_lib.tournament(5, 3, j, 1, N) < N // 2
+        tab[int(a), int(b)] += 1
+    e = np.outer(tab.sum(1), tab.sum(0)) / tab.sum()
+    assert float(((tab - e) ** 2 / e).sum()) < 10.83
+
+
+@pytest.mark.parametrize("cp,es", [(0.9, 4), (0.5, 3), (0.2, 8), (0.8, 1)])
+def test_crossover_gate_frequency(oracle_lib, cp, es):
+    """Alg. 2 crosses over when its uniform draw x satisfies x <= C_P (probability C_P) and
+    otherwise copies one parent, each of the E_S with probability 1 / E_S. An inverted gate
+    (crossover with probability 1 - C_P) must fail the binomial bound."""
+    n = 40000
+    gates = np.array([oracle_lib.gate(seed=2, gen=1 + j % 50, j=j // 50, crossover_p=cp,
+                                      parents_per_child=es) for j in range(n)])
+    assert ((gates >= -1) & (gates < es)).all()
+    frac = np.count_nonzero(gates == -1) / n
+    sd = np.sqrt(cp * (1 - cp) / n)
+    assert abs(frac - cp) < 5 * sd
+    assert abs(frac - (1 - cp)) > 5 * sd or cp == 0.5
+    copies = np.bincount(gates[gates >= 0], minlength=es)
+    if es > 1:
+        crit = {3: 13.82, 4: 16.27, 8: 24.32}[es]
+        assert _chi2(copies, np.full(es, 1.0 / es)) < crit
+    assert all(oracle_lib.gate(2, 1, j, 0.0, es) >= 0 for j in range(500))
+    assert all(oracle_lib.gate(2, 1, j, 1.0, es) == -1 for j in range(500))
+
+
+def test_run_copies_only_without_crossover_and_mutation(oracle_lib):
+    """With C_P = 0 and M_P = 0 every offspring is a copy of a parent, so every row of every
+    P(g) is a row of the initial population P(0)."""
+    g = synth.small_1k()
+    states = []
+    oracle_lib.run(g.row_ptr, g.col, pop_size=16, generations=8, crossover_p=0.0,
+                   mutation_p=0.0, seed=4, on_generation=states.append)
+    rows0 = {r.tobytes() for r in states[0].labels}
+    assert len(rows0) > 1
+    for s in states[1:]:
+        for r in s.labels:
+            assert r.tobytes() in rows0
+
+
+def _reordered_previous(oracle_lib, g, prev, cur):
+    """P(g-1) of a trace reordered by its own rank and crowding (Alg. 1 SortByRankAndDistance),
+    checked against the rank / crowding the run reports at generation g."""
+    m2 = 2 * g.m
+    k1, k2 = m2 - prev.A, prev.S
+    r = oracle_lib.rank(k1, k2)
+    cd = oracle_lib.crowding(r, k1, k2, prev.f1, prev.f2)
+    o = oracle_lib.order(r, cd)
+    assert (r[o] == cur.rank).all()
+    assert (cd[o].view(np.uint64) == cur.crowd.view(np.uint64)).all()
+    return prev.labels[o]
+
+
+@pytest.mark.parametrize("es", [1, 3, 4])
+def test_run_crossover_only_children_are_parent_pluralities(oracle_lib, es):
+    """With C_P = 1 and M_P = 0 every offspring is the ensemble crossover of its E_S
+    tournament winners: at every node the child's label has the maximal multiplicity among
+    the parents' labels there (eq. arg_max), and the next population consists of members
+    of the previous one and of these children only."""
+    g = synth.small_1k()
+    states = []
+    Np = 12
+    kw = dict(crossover_p=1.0, mutation_p=0.0, parents_per_child=es, seed=9)
+    oracle_lib.run(g.row_ptr, g.col, pop_size=Np, generations=5, on_generation=states.append,
+                   **kw)
+    for prev, cur in zip(states, states[1:]):
+        P = _reordered_previous(oracle_lib, g, prev, cur)
+        kids = set()
+        for j in range(Np):
+            child, pos, gate = oracle_lib.offspring(g.row_ptr, g.col, P, es, 1.0, 0.0, 9,
+                                                    cur.g, j)
+            assert gate == -1 and ((pos >= 0) & (pos < Np)).all()
+            par = P[pos]                                   # (es, n)
+            mult = (par[:, None, :] == par[None, :, :]).sum(1)   # multiplicity of each label
+            assert (((par == child[None, :]).sum(0)) == mult.max(0)).all()
+            if es == 1:
+                assert (child == par[0]).all()
+            kids.add(child.tobytes())
+        allowed = kids | {r.tobytes() for r in P}
+        for r in cur.labels:
+            assert r.tobytes() in allowed
+
+
+def test_run_copy_gate_children_are_their_parents(oracle_lib):
+    """With C_P = 0 the gate copies parent slot pick(w1, E_S); with M_P = 0 the offspring is
+    that parent's row unchanged."""
+    g = synth.appendix_graph()
+    rng = np.random.default_rng(3)
+    P = rng.integers(0, g.n, size=(9, g.n)).astype(np.int32)
+    for j in range(40):
+        child, pos, gate = oracle_lib.offspring(g.row_ptr, g.col, P, 4, 0.0, 0.0, 1, 2, j)
+        assert 0 <= gate < 4
+        assert (child == P[pos[gate]]).all()
