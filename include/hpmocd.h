@@ -39,6 +39,7 @@ extern "C" {
 #define HPMOCD_ERR_NOMEM -11     /* host allocation failed */
 #define HPMOCD_ERR_CANCELLED -12 /* server request cancelled (or the server shut down first) */
 #define HPMOCD_ERR_TIMEOUT -13   /* server wait timed out; the request is still pending */
+#define HPMOCD_ERR_SCRATCH -14   /* problem larger than hpmocd_eval_noalloc's fixed scratch */
 
 /* Largest population: the selection kernels rank 2 * pop_size points in one workgroup. */
 #define HPMOCD_MAX_POP 512
@@ -199,6 +200,24 @@ int hpmocd_eval_workspace_size(const hpmocd_graph *g, int32_t n_ind, size_t *byt
 int hpmocd_eval(const hpmocd_graph *g, const int32_t *d_labels, int32_t n_ind,
                 void *d_workspace, size_t ws_bytes, void *stream, int64_t *A, int64_t *S,
                 double *f1, double *f2, double *kernel_ms);
+
+/* hpmocd_eval for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same kernels and
+ * results, bit for bit, with the workspace taken from a fixed device array of
+ * HPMOCD_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs on until the
+ * process ends, instead of a caller workspace. The call allocates no device memory (no
+ * hipMalloc, no hipFree, no allocating library routine). d_labels: device memory, row-major
+ * n_ind x n int32 labels in [0, n), on the graph's device, which must be current. A, S, f1,
+ * f2: host arrays of n_ind, written only on success. Errors: HPMOCD_ERR_ARG (null pointer,
+ * n_ind < 1, another device current), HPMOCD_ERR_SCRATCH when hpmocd_eval_workspace_size
+ * (g, n_ind) exceeds HPMOCD_NOALLOC_SCRATCH_BYTES (e.g. 40,000 nodes x 100 partitions fits,
+ * 1,000,000 x 100 does not), HPMOCD_ERR_RANGE for a label outside [0, n), HPMOCD_ERR_HIP.
+ * Every call on one device shares that device's array (each call clears what it
+ * accumulates into): calls that overlap on one device, from several host threads or on
+ * several streams, race and must be serialised by the caller. */
+#define HPMOCD_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int hpmocd_eval_noalloc(const hpmocd_graph *g, const int32_t *d_labels, int32_t n_ind,
+                        void *stream, int64_t *A, int64_t *S, double *f1, double *f2);
 
 /* Served form: a community-detection service over one device. Requests (a CSR graph plus
  * Alg. 1 parameters) are submitted from any host thread and return at once with a ticket;

@@ -21,13 +21,15 @@ ERR = {
     -1: "ERR_ARG", -2: "ERR_CSR_ASYM", -3: "ERR_SELF_LOOP", -4: "ERR_DUP_EDGE",
     -5: "ERR_RANGE", -6: "ERR_EMPTY", -7: "ERR_TOO_LARGE", -8: "ERR_WORKSPACE",
     -9: "ERR_HIP", -10: "ERR_BUDGET", -11: "ERR_NOMEM", -12: "ERR_CANCELLED",
-    -13: "ERR_TIMEOUT",
+    -13: "ERR_TIMEOUT", -14: "ERR_SCRATCH",
 }
 ERR_ARG = -1
 ERR_RANGE = -5
 ERR_BUDGET = -10
 ERR_CANCELLED = -12
 ERR_TIMEOUT = -13
+ERR_SCRATCH = -14
+NOALLOC_SCRATCH_BYTES = 64 << 20
 MAX_POP = 512
 MAX_PARENTS = 8
 NO_GRAPH = 1
@@ -48,6 +50,7 @@ EXPORTS = [
     "hpmocd_server_poll", "hpmocd_server_wait", "hpmocd_server_cancel",
     "hpmocd_server_stats_get", "hpmocd_server_destroy",
     "hpmocd_run_to", "hpmocd_resume", "hpmocd_snapshot_free",
+    "hpmocd_eval_noalloc",
 ]
 
 
@@ -150,6 +153,7 @@ def lib():
         L.hpmocd_eval_workspace_size.argtypes = [vp, C.c_int32, C.POINTER(C.c_size_t)]
         L.hpmocd_eval.argtypes = [vp, vp, C.c_int32, vp, C.c_size_t, vp, i64p, i64p, f64p, f64p,
                                   f64p]
+        L.hpmocd_eval_noalloc.argtypes = [vp, vp, C.c_int32, vp, i64p, i64p, f64p, f64p]
         L.hpmocd_batch_workspace_size.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(Params),
                                                   C.c_int, C.POINTER(C.c_size_t)]
         L.hpmocd_run_batch.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(Params), vp,
@@ -449,6 +453,27 @@ def evaluate(graph: Graph, labels, *, stream=None, timing=False):
                              f2.ctypes.data_as(C.POINTER(C.c_double)), C.byref(ms)),
            "hpmocd_eval")
     return (A, S, f1, f2, ms.value) if timing else (A, S, f1, f2)
+
+
+def evaluate_noalloc(graph: Graph, labels, *, stream=None):
+    """hpmocd_eval_noalloc: hpmocd_eval with the library's fixed device scratch (no
+    workspace, no device allocation); labels as for evaluate()."""
+    import torch
+    assert labels.is_cuda and labels.dtype == torch.int32 and labels.is_contiguous()
+    n_ind = labels.shape[0]
+    assert labels.shape[1] == graph.n
+    A = np.empty(n_ind, dtype=np.int64)
+    S = np.empty(n_ind, dtype=np.int64)
+    f1 = np.empty(n_ind, dtype=np.float64)
+    f2 = np.empty(n_ind, dtype=np.float64)
+    _check(lib().hpmocd_eval_noalloc(graph.handle, C.c_void_p(labels.data_ptr()), n_ind,
+                                     _stream_handle(stream),
+                                     A.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     S.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     f1.ctypes.data_as(C.POINTER(C.c_double)),
+                                     f2.ctypes.data_as(C.POINTER(C.c_double))),
+           "hpmocd_eval_noalloc")
+    return A, S, f1, f2
 
 
 class Server:

@@ -221,6 +221,7 @@ const char *hpmocd_strerror(int status)
     case HPMOCD_ERR_NOMEM: return "host allocation failed";
     case HPMOCD_ERR_CANCELLED: return "request cancelled";
     case HPMOCD_ERR_TIMEOUT: return "wait timed out";
+    case HPMOCD_ERR_SCRATCH: return "problem exceeds the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
     }
 }

@@ -181,16 +181,24 @@ size_t meta_bytes(int32_t count)
            align_up(sizeof(int32_t) * (size_t)N_KINDS * ((size_t)count + 1));
 }
 
-int Meta::upload(const std::vector<Item> &host_items, void *region, hipStream_t s)
+int Meta::upload(const Item *host_items, int32_t n_items, void *region, hipStream_t s)
 {
-    count = (int32_t)host_items.size();
+    count = n_items;
     items = (Item *)region;
     starts = (int32_t *)((char *)region + align_up(sizeof(Item) * (size_t)count));
-    h_items = host_items;
-    h_starts.assign((size_t)N_KINDS * ((size_t)count + 1), 0);
-    std::vector<int32_t> &st = h_starts;
+    const size_t n_starts = (size_t)N_KINDS * ((size_t)count + 1);
+    Item *hi = &h_item1;
+    int32_t *st = h_starts1;
+    if (count == 1) {
+        h_item1 = host_items[0];
+    } else {
+        h_items.assign(host_items, host_items + count);
+        h_starts.assign(n_starts, 0);
+        hi = h_items.data();
+        st = h_starts.data();
+    }
     for (int k = 0; k < N_KINDS; ++k) {
-        int32_t *row = st.data() + (size_t)k * (count + 1);
+        int32_t *row = st + (size_t)k * (count + 1);
         int64_t acc = 0;
         lds[k] = 0;
         aux[k] = 0;
@@ -204,8 +212,8 @@ int Meta::upload(const std::vector<Item> &host_items, void *region, hipStream_t 
         if (acc > 0x7fffffff) return HPMOCD_ERR_ARG;
         totals[k] = (int32_t)acc;
     }
-    HIP_TRY(hipMemcpyAsync(items, h_items.data(), sizeof(Item) * (size_t)count, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(starts, st.data(), sizeof(int32_t) * st.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(items, hi, sizeof(Item) * (size_t)count, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(starts, st, sizeof(int32_t) * n_starts, hipMemcpyHostToDevice, s));
     return HPMOCD_OK;
 }
 
@@ -901,6 +909,91 @@ int hpmocd_resume(const hpmocd_graph *G, const hpmocd_params *p, const hpmocd_sn
     return rc;
 }
 
+}  // extern "C"
+
+namespace hpm {
+
+int eval_on(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, void *ws,
+            hipStream_t s, int64_t *A, int64_t *S, double *f1, double *f2, double *kernel_ms)
+{
+    DrainOnExit drain{s};
+    const int32_t ld = round16(n_ind);
+    const size_t plane = (size_t)G->n * ld * 4;
+    char *p = (char *)ws;
+    int32_t *lab = (int32_t *)p;
+    p += align_up(plane);
+    Item it{};
+    it.g = dev_graph(G);
+    const Tuning t;
+    it.hp = hist_plan(G->n, n_ind, G->max_deg, t.hist_min_log2, t.hist_rbits,
+                      t.hist_narrow != 0);
+    if (it.hp.enabled) {
+        it.run = (uint32_t *)p;
+        p += align_up(it.hp.entries * 4);
+        it.off = (uint32_t *)p;
+        p += align_up(it.hp.offsets * 4);
+    } else {
+        it.D = (int32_t *)p;
+        it.D_bytes = plane;
+        p += align_up(plane);
+    }
+    unsigned long long *dA = (unsigned long long *)p;
+    p += align_up(8 * (size_t)n_ind);
+    unsigned long long *dS = (unsigned long long *)p;
+    p += align_up(8 * (size_t)n_ind);
+    double *df1 = (double *)p;
+    p += align_up(8 * (size_t)n_ind);
+    double *df2 = (double *)p;
+    p += align_up(8 * (size_t)n_ind);
+    int32_t *d_bad = (int32_t *)p;
+    p += align_up(sizeof(int32_t));
+    it.lab = lab;
+    it.fit_pop = n_ind;
+    it.fit_ld = ld;
+    it.fit_A = dA;
+    it.fit_S = dS;
+    it.fit_npw = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, G->n / t.fit_target_waves));
+    it.xo_nb = 1;
+    it.c.pop = n_ind;
+    Meta m;
+    int rc = m.upload(&it, 1, p, s);
+    if (rc) return rc;
+    // everything the kernels accumulate into starts at zero: the plain histogram plane, the
+    // A / S accumulators and the label-range flag (the binned areas are overwritten whole)
+    HIP_TRY(m.launch(K_CLEAR, s));
+    HIP_TRY(m.one(ONE_ZERO_ACC, s));
+    HIP_TRY(hipMemsetAsync(d_bad, 0, sizeof(int32_t), s));
+    HIP_TRY(launch_transpose_in(d_labels, G->n, n_ind, ld, lab, d_bad, s));
+    EventSet evs;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (kernel_ms) {
+        a = evs.make();
+        b = evs.make();
+        if (!a || !b) return HPMOCD_ERR_HIP;
+        HIP_TRY(hipEventRecord(a, s));
+    }
+    HIP_TRY(launch_fitness_kinds(m, s, nullptr));
+    if (kernel_ms) HIP_TRY(hipEventRecord(b, s));
+    HIP_TRY(launch_finalize(G->m2, n_ind, dA, dS, df1, df2, s));
+    // A and S are non-negative counts below 2^63: the unsigned accumulators' bits are the
+    // int64 values, copied straight into the caller's arrays
+    int32_t bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bad) return HPMOCD_ERR_RANGE;  // evaluated with those labels replaced by 0
+    HIP_TRY(hipMemcpyAsync(A, dA, sizeof(int64_t) * n_ind, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(S, dS, sizeof(int64_t) * n_ind, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(f1, df1, sizeof(double) * n_ind, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(f2, df2, sizeof(double) * n_ind, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (kernel_ms) *kernel_ms = elapsed(a, b);
+    return HPMOCD_OK;
+}
+
+}  // namespace hpm
+
+extern "C" {
+
 // ---------------------------------------------------------------------------------------
 // fitness alone (eval)
 // ---------------------------------------------------------------------------------------
@@ -930,80 +1023,7 @@ int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, v
     size_t need = 0;
     hpmocd_eval_workspace_size(G, n_ind, &need);
     if (ws_bytes < need) return HPMOCD_ERR_WORKSPACE;
-    hipStream_t s = (hipStream_t)stream;
-    DrainOnExit drain{s};
-    const int32_t ld = round16(n_ind);
-    const size_t plane = (size_t)G->n * ld * 4;
-    char *p = (char *)ws;
-    int32_t *lab = (int32_t *)p;
-    p += align_up(plane);
-    Item it{};
-    it.g = dev_graph(G);
-    const Tuning tdef;
-    it.hp = hist_plan(G->n, n_ind, G->max_deg, tdef.hist_min_log2, tdef.hist_rbits,
-                      tdef.hist_narrow != 0);
-    if (it.hp.enabled) {
-        it.run = (uint32_t *)p;
-        p += align_up(it.hp.entries * 4);
-        it.off = (uint32_t *)p;
-        p += align_up(it.hp.offsets * 4);
-    } else {
-        it.D = (int32_t *)p;
-        it.D_bytes = plane;
-        p += align_up(plane);
-    }
-    unsigned long long *dA = (unsigned long long *)p;
-    p += align_up(8 * (size_t)n_ind);
-    unsigned long long *dS = (unsigned long long *)p;
-    p += align_up(8 * (size_t)n_ind);
-    double *df1 = (double *)p;
-    p += align_up(8 * (size_t)n_ind);
-    double *df2 = (double *)p;
-    p += align_up(8 * (size_t)n_ind);
-    int32_t *d_bad = (int32_t *)p;
-    p += align_up(sizeof(int32_t));
-    it.lab = lab;
-    it.fit_pop = n_ind;
-    it.fit_ld = ld;
-    it.fit_A = dA;
-    it.fit_S = dS;
-    Tuning t;
-    it.fit_npw = (int32_t)std::max<int64_t>(1, std::min<int64_t>(64, G->n / t.fit_target_waves));
-    it.xo_nb = 1;
-    it.c.pop = n_ind;
-    Meta m;
-    std::vector<Item> items(1, it);
-    if ((rc = m.upload(items, p, s))) return rc;
-    HIP_TRY(m.launch(K_CLEAR, s));
-    HIP_TRY(m.one(ONE_ZERO_ACC, s));
-    HIP_TRY(hipMemsetAsync(d_bad, 0, sizeof(int32_t), s));
-    HIP_TRY(launch_transpose_in(d_labels, G->n, n_ind, ld, lab, d_bad, s));
-    EventSet evs;
-    hipEvent_t a = nullptr, b = nullptr;
-    if (kernel_ms) {
-        a = evs.make();
-        b = evs.make();
-        if (!a || !b) return HPMOCD_ERR_HIP;
-        HIP_TRY(hipEventRecord(a, s));
-    }
-    HIP_TRY(launch_fitness_kinds(m, s, nullptr));
-    if (kernel_ms) HIP_TRY(hipEventRecord(b, s));
-    HIP_TRY(launch_finalize(G->m2, n_ind, dA, dS, df1, df2, s));
-    std::vector<unsigned long long> hA(n_ind), hS(n_ind);
-    int32_t bad = 0;
-    HIP_TRY(hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hA.data(), dA, sizeof(unsigned long long) * n_ind, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(hS.data(), dS, sizeof(unsigned long long) * n_ind, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(f1, df1, sizeof(double) * n_ind, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(f2, df2, sizeof(double) * n_ind, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (bad) return HPMOCD_ERR_RANGE;  // evaluated with those labels replaced by 0
-    for (int32_t i = 0; i < n_ind; ++i) {
-        A[i] = (int64_t)hA[i];
-        S[i] = (int64_t)hS[i];
-    }
-    if (kernel_ms) *kernel_ms = elapsed(a, b);
-    return HPMOCD_OK;
+    return eval_on(G, d_labels, n_ind, ws, (hipStream_t)stream, A, S, f1, f2, kernel_ms);
 }
 
 }  // extern "C"

@@ -78,6 +78,8 @@ struct Pop {
 struct Meta {
     std::vector<Item> h_items;
     std::vector<int32_t> h_starts;
+    Item h_item1{};                       // staging of a one-item table (no host allocation)
+    int32_t h_starts1[2 * N_KINDS] = {};
     Item *items = nullptr;
     int32_t *starts = nullptr;
     int32_t count = 0;
@@ -85,7 +87,11 @@ struct Meta {
     size_t lds[N_KINDS] = {};
     int32_t aux[N_KINDS] = {};
     Span span(Kind k) const { return Span{items, starts + (size_t)k * (count + 1), count}; }
-    int upload(const std::vector<Item> &host_items, void *region, hipStream_t s);
+    int upload(const Item *host_items, int32_t n_items, void *region, hipStream_t s);
+    int upload(const std::vector<Item> &host_items, void *region, hipStream_t s)
+    {
+        return upload(host_items.data(), (int32_t)host_items.size(), region, s);
+    }
     hipError_t launch(Kind k, hipStream_t s) const;
     hipError_t one(OneKernel which, hipStream_t s) const;
 };
@@ -122,6 +128,12 @@ hipError_t launch_generation(const Meta &m, hipStream_t s, const EventPair *ev, 
 int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, void *user,
                bool with_labels);
 int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out);
+
+// Fitness of n_ind device label rows with the eval workspace at ws (hpmocd_eval_workspace_size
+// bytes, contents on entry irrelevant); results to host arrays. No device or host allocation
+// unless kernel_ms is requested (its events).
+int eval_on(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, void *ws,
+            hipStream_t s, int64_t *A, int64_t *S, double *f1, double *f2, double *kernel_ms);
 
 // A whole batched run (init, T generations, fronts); a single run is a batch of one.
 int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_params *params,
