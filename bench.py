@@ -2,11 +2,15 @@
 
 One step = one whole run of the method (initialisation, T generations of tournament ->
 crossover -> mutation -> fitness -> environmental selection, front extraction) on a
-synthetic planted-partition graph already resident in HBM. The reported value is the
-fitness throughput in edge-evaluations per second (one undirected edge tested for one
-individual; one individual evaluation = m edge-evaluations), from HIP events recorded by the
-library around every fitness launch on the run's stream; generations per second come from
-events around the generation loop.
+synthetic planted-partition graph already resident in HBM, through the production entry
+point (hpmocd_run: the generation loop replayed from a hipGraph). The timed region is K such
+runs: ms_per_step is their wall time, gens_per_s comes from HIP events around their
+generation loops. The reported value is the fitness throughput in edge-evaluations per
+second (one undirected edge tested for one individual; one individual evaluation = m
+edge-evaluations) over the fitness kernels' own device time, which a second pass of K runs
+in the same process measures with HIP events the library records around every fitness
+launch (kernels launched one by one); that pass also gives the per-kernel-group breakdown
+and the roofline figures.
 
 Prints one JSON line. ``--gpus N`` with N > 1 is refused: this build targets one GPU.
 """
@@ -112,10 +116,40 @@ def cpu_baseline(g, seed: int, target_s: float = 15.0):
                       f"({reps * k} individual evaluations), serial C oracle, {dt:.2f} s"}
 
 
+def host_cpu():
+    """The host CPU as the OS reports it: model name (every distinct /proc/cpuinfo entry,
+    plus family / model / stepping numbers), logical CPUs, the CPUs this process may run on,
+    and the OpenMP thread count the environment grants."""
+    info = {"model_names": [], "family_model_stepping": None, "logical_cpus": os.cpu_count(),
+            "cpus_available": None, "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+    try:
+        info["cpus_available"] = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        pass
+    fam = mod = step = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            key, _, val = line.partition(":")
+            key, val = key.strip(), val.strip()
+            if key == "model name" and val not in info["model_names"]:
+                info["model_names"].append(val)
+            elif key == "cpu family" and fam is None:
+                fam = val
+            elif key == "model" and mod is None:
+                mod = val
+            elif key == "stepping" and step is None:
+                step = val
+    except OSError:
+        pass
+    if fam is not None:
+        info["family_model_stepping"] = f"{fam}/{mod}/{step}"
+    return info
+
+
 def cpu_generation(g, kw, threads: int):
     """Context beside cpu_baseline: one whole oracle generation (tournament, crossover,
-    mutation, evaluation, selection) with OpenMP over individuals on the host's cores, as the
-    difference of a one-generation run and a zero-generation run."""
+    mutation, evaluation, selection), as the difference of a one-generation run and a
+    zero-generation run, with OpenMP over individuals on `threads` threads."""
     import oracle
     oracle.build()
 
@@ -125,16 +159,7 @@ def cpu_generation(g, kw, threads: int):
         return time.perf_counter() - t0
     t0 = timed(0)
     t1 = timed(1)
-    model = "?"
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                model = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    return {"seconds_per_generation": max(t1 - t0, 1e-9), "threads": threads,
-            "cpu_model": model, "kind": "oracle"}
+    return max(t1 - t0, 1e-9)
 
 
 def bench_batched(args):
@@ -169,6 +194,12 @@ def bench_batched(args):
     t_batch = time.perf_counter() - t0
     print(f"# batched {t_batch:.3f} s (autotune probes {prof['tune_probe_ms']:.1f} ms)",
           file=sys.stderr, flush=True)
+    if args.no_sequential:   # the batched call alone (for a kernel trace of its loop)
+        print(json.dumps({"metric": "batched runs/s (pop 64, 100 generations per run)",
+                          "value": len(dgs) / t_batch, "unit": "runs/s", "n_gpus": 1,
+                          "batched_loop_ms": prof["loop_ms"],
+                          "autotune_probe_ms": prof["tune_probe_ms"]}), flush=True)
+        return
     single_ws = torch.empty(max(hp.workspace_size(d, params) for d in dgs), dtype=torch.uint8,
                             device="cuda")
     torch.cuda.synchronize()
@@ -373,6 +404,10 @@ def bench_served(args):
     cap = count / mk
     out["capacity"] = summary(lat, mk, st)
     print(f"# capacity (all at t=0): {cap:.2f} runs/s", file=sys.stderr, flush=True)
+    if args.served_capacity_only:   # one pass (for a kernel trace of the served loop)
+        print(json.dumps({"metric": "served capacity runs/s", "value": cap, "unit": "runs/s",
+                          "n_gpus": 1, "detail": out}), flush=True)
+        return
     _, lat, mk, st = serve(True, None)
     out["fifo_capacity"] = summary(lat, mk, st)
     print(f"# FIFO capacity: {count / mk:.2f} runs/s", file=sys.stderr, flush=True)
@@ -420,8 +455,6 @@ def main():
     ap.add_argument("--generations", type=int, default=100)
     ap.add_argument("--pop", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--graph-mode", action="store_true",
-                    help="also time runs whose generation loop is replayed from a hipGraph")
     ap.add_argument("--batched", type=int, default=0, metavar="COUNT",
                     help="batched form instead: COUNT planted-partition graphs (|V| log-uniform "
                          "in [500, 50000]), pop 64, in one batched run vs COUNT sequential runs")
@@ -437,6 +470,10 @@ def main():
                     help="the paper's LFR setting (n 20,000, mean degree 20, max 50, communities "
                          "20-100, mu 0.3; pop 100, 100 generations, C_P 0.8, M_P 0.2, E_S 4) end "
                          "to end, next to the paper's reported runtime")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="with --batched: time the batched call only (no sequential baseline)")
+    ap.add_argument("--served-capacity-only", action="store_true",
+                    help="with --served: run the capacity pass only (all requests at t = 0)")
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -482,8 +519,22 @@ def main():
     print(f"# workload {args.workload}: n={g.n} m={g.m} pop={args.pop} T={args.generations}",
           file=sys.stderr, flush=True)
 
+    # the production path: hpmocd_run with its generation loop replayed from a hipGraph
     for _ in range(args.warmup):
-        hp.run(dg, params, stream=stream, workspace=ws, flags=hp.TIME_KERNELS, profile=True)
+        hp.run(dg, params, stream=stream, workspace=ws, profile=True)
+    torch.cuda.synchronize()
+    loops = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, prof = hp.run(dg, params, stream=stream, workspace=ws, profile=True)
+        loops.append(prof["loop_ms"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print(f"# timed {args.steps} hipGraph-replayed runs in {wall:.3f} s", file=sys.stderr,
+          flush=True)
+
+    # the kernel-timing pass: the same runs with events around every kernel group
+    hp.run(dg, params, stream=stream, workspace=ws, flags=hp.TIME_KERNELS, profile=True)
     torch.cuda.synchronize()
     profs = []
     t0 = time.perf_counter()
@@ -492,8 +543,9 @@ def main():
                          profile=True)
         profs.append(prof)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    print(f"# timed {args.steps} runs in {wall:.3f} s", file=sys.stderr, flush=True)
+    wall_k = time.perf_counter() - t0
+    print(f"# kernel-timing pass: {args.steps} runs in {wall_k:.3f} s", file=sys.stderr,
+          flush=True)
 
     T, pop = args.generations, args.pop
     launches = sum(p["fitness_launches"] for p in profs)
@@ -505,7 +557,9 @@ def main():
     value = edge_evals / ((fit_ms + sweep_ms) / 1e3)
     eval_ms = (fit_ms + sweep_ms) / launches      # one whole-population evaluation
     bytes_launch = pop * per_individual_bytes(g.n, 2 * g.m)
+    floor_launch = population_floor_bytes(g.n, 2 * g.m, pop)
     achieved = bytes_launch / (eval_ms / 1e3) / 1e9
+    traffic = measured_traffic(args.workload, pop)
     copy_gbps = copy_ceiling_gbps()
     out = {
         "metric": METRIC,
@@ -526,7 +580,14 @@ def main():
                    "generations": T, "crossover_p": kw["crossover_p"],
                    "mutation_p": kw["mutation_p"], "parents_per_child": kw["parents_per_child"],
                    "seed": kw["seed"], "graph_seed": 0},
-        "gens_per_s": T * args.steps / (loop_ms / 1e3) if T else None,
+        "gens_per_s": T * args.steps / (sum(loops) / 1e3) if T else None,
+        "timed_path": "hpmocd_run, generation loop replayed from a hipGraph (production)",
+        "kernel_timing_pass": {
+            "what": "the same runs launched kernel by kernel with HIP events around every "
+                    "kernel group (HPMOCD_TIME_KERNELS): value, the breakdown below, roofline",
+            "ms_per_step": wall_k * 1e3 / args.steps,
+            "gens_per_s": T * args.steps / (loop_ms / 1e3) if T else None},
+        "end_to_end_edge_evals_per_s": edge_evals / wall if wall > 0 else None,
         "fitness_ms_per_population": eval_ms,
         "histogram_clear_ms_per_population": sweep_ms / launches,
         "variation_ms_per_gen": sum(p["variation_ms"] for p in profs) / max(1, T * args.steps),
@@ -535,25 +596,32 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "fitness step (k_bin, then k_fitness beside k_hist)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": measured_traffic(args.workload, pop),
+                     "traffic": traffic,
                      "bytes_per_launch": bytes_launch, "ms_per_launch": eval_ms,
+                     # the same duration against the bytes the counters saw move (L2 misses
+                     # to the memory fabric) and against the compulsory bytes of one
+                     # population pass (CSR once + every label row once)
+                     "frac_physical": (traffic / (eval_ms / 1e3) / 1e9 / HBM_PEAK_GBPS
+                                       if traffic else None),
+                     "floor_bytes_per_launch": floor_launch,
+                     "frac_floor": floor_launch / (eval_ms / 1e3) / 1e9 / HBM_PEAK_GBPS,
                      "l2_hit_rate": measured_counter(args.workload, pop, "fitness_l2_hit_rate"),
                      "copy_ceiling_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps},
     }
-    if args.graph_mode and T >= 2:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        loops = []
-        for _ in range(args.steps):
-            _, p = hp.run(dg, params, stream=stream, workspace=ws, profile=True)
-            loops.append(p["loop_ms"])
-        torch.cuda.synchronize()
-        out["graph_mode"] = {"ms_per_step": (time.perf_counter() - t0) * 1e3 / args.steps,
-                             "gens_per_s": T * args.steps / (sum(loops) / 1e3)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, kw["seed"])
-        # at most 16 host threads: a job's CPU share on a one-GPU host, whatever the core count shows
-        out["cpu_oracle_generation"] = cpu_generation(g, kw, min(16, os.cpu_count() or 1))
+        host = host_cpu()
+        avail = host["cpus_available"] or host["logical_cpus"] or 1
+        # OpenMP threads: the environment's grant (a one-GPU job's share of the host), else
+        # every CPU this process may run on
+        threads = int(host["omp_num_threads_env"] or avail)
+        threads = max(1, min(threads, avail))
+        out["cpu_oracle_generation"] = {
+            "seconds_per_generation": cpu_generation(g, kw, threads), "threads": threads,
+            "seconds_per_generation_1_thread": cpu_generation(g, kw, 1),
+            "threads_reason": "OMP_NUM_THREADS of the environment (the host share granted to a "
+                              "one-GPU job), capped by the CPUs this process may use",
+            "host": host, "kind": "oracle"}
     print(json.dumps(out), flush=True)
 
 

@@ -98,3 +98,28 @@ def test_batch_rejects_mixed_generations(hp):
     dg = hp.Graph(g.row_ptr, g.col)
     with pytest.raises(hp.HpmocdError):
         hp.run_batch([dg, dg], [hp.make_params(generations=3), hp.make_params(generations=4)])
+
+
+def test_batch_largest_benchmark_graphs_full_run_against_oracle(hp):
+    """The batched benchmark's own graphs at full size: its three largest graphs (|V| about
+    48,000-49,000) and its three smallest, pop 64, 100 generations, autotuned launch shapes
+    as in the benchmark: every front equals the oracle's bit for bit."""
+    import os
+
+    import torch
+    s = torch.cuda.Stream()
+    ps = synth.batch_params(256, seed=0)
+    by_n = sorted(range(len(ps)), key=lambda i: ps[i]["n"])
+    pick = by_n[-3:] + by_n[:3]
+    graphs = [synth.batch_graph(ps[i]) for i in pick]
+    print(f"benchmark graphs {pick}: n = {[g.n for g in graphs]}", flush=True)
+    dgs = [hp.Graph(g.row_ptr, g.col) for g in graphs]
+    p = hp.make_params(pop_size=64, generations=100, crossover_p=0.9, mutation_p=0.1,
+                       parents_per_child=4, seed=0)
+    fronts = hp.run_batch(dgs, p, stream=s, flags=hp.AUTOTUNE)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    for i, g in zip(pick, graphs):
+        ref = oracle.run(g.row_ptr, g.col, pop_size=64, generations=100, crossover_p=0.9,
+                         mutation_p=0.1, parents_per_child=4, seed=0, threads=threads)
+        print(f"  graph {i} (n={g.n}, m={g.m}): front {len(ref.A)}", flush=True)
+        assert same(fronts[pick.index(i)], ref), f"benchmark graph {i} differs from the oracle"
