@@ -125,6 +125,9 @@ int hpmocd_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *col,
 void hpmocd_graph_destroy(hpmocd_graph *g);
 /* n, number of arcs (2m) and the largest degree. Any out-pointer may be NULL. */
 int hpmocd_graph_info(const hpmocd_graph *g, int32_t *n, int64_t *arcs, int32_t *max_deg);
+/* 64-bit fingerprint of the graph (FNV-1a over n and the sorted CSR): equal graphs, given in
+ * any adjacency order, have equal fingerprints. */
+int hpmocd_graph_hash(const hpmocd_graph *g, uint64_t *hash);
 
 /* Bytes of device workspace hpmocd_run needs for these parameters (256-byte aligned). */
 int hpmocd_workspace_size(const hpmocd_graph *g, const hpmocd_params *p, size_t *bytes);
@@ -178,6 +181,8 @@ typedef struct {
     int32_t pop_size, n_nodes;
     int32_t *labels;      /* pop_size x n_nodes, row-major, in selection order */
     int64_t *A, *S;       /* objectives' integer numerators of each member */
+    hpmocd_params params; /* the run's parameters (generations may differ on resume) */
+    uint64_t graph_hash;  /* fingerprint of the graph (hpmocd_graph_hash) */
 } hpmocd_snapshot;
 
 /* Runs initialisation and generations 1..stop_gen (0 <= stop_gen <= p->generations) and
@@ -186,8 +191,11 @@ int hpmocd_run_to(const hpmocd_graph *g, const hpmocd_params *p, int32_t stop_ge
                   void *d_workspace, size_t ws_bytes, void *stream, hpmocd_snapshot **out);
 /* Continues a run from a snapshot taken with the same graph and parameters: generations
  * snap->g + 1 .. p->generations, then the front. The result equals the uninterrupted
- * hpmocd_run bit for bit. The snapshot is validated (sizes, g <= T, labels in [0, n)) before
- * any device work. */
+ * hpmocd_run bit for bit. Validation: sizes, g <= T, labels in [0, n), the graph's
+ * fingerprint and every parameter but the generation count equal to the snapshot's
+ * (HPMOCD_ERR_ARG otherwise) before any device work; then the fitness kernels re-evaluate
+ * the snapshot's labels, and A or S differing from the stored values gives HPMOCD_ERR_ARG
+ * (the objectives would not belong to the labels). */
 int hpmocd_resume(const hpmocd_graph *g, const hpmocd_params *p, const hpmocd_snapshot *snap,
                   void *d_workspace, size_t ws_bytes, void *stream, hpmocd_front **out);
 void hpmocd_snapshot_free(hpmocd_snapshot *s);

@@ -50,7 +50,7 @@ EXPORTS = [
     "hpmocd_server_poll", "hpmocd_server_wait", "hpmocd_server_cancel",
     "hpmocd_server_stats_get", "hpmocd_server_destroy",
     "hpmocd_run_to", "hpmocd_resume", "hpmocd_snapshot_free",
-    "hpmocd_eval_noalloc",
+    "hpmocd_eval_noalloc", "hpmocd_graph_hash",
 ]
 
 
@@ -95,10 +95,12 @@ class Profile(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+
+
 class _Snapshot(C.Structure):
     _fields_ = [("g", C.c_int32), ("pop_size", C.c_int32), ("n_nodes", C.c_int32),
                 ("labels", C.POINTER(C.c_int32)), ("A", C.POINTER(C.c_int64)),
-                ("S", C.POINTER(C.c_int64))]
+                ("S", C.POINTER(C.c_int64)), ("params", Params), ("graph_hash", C.c_uint64)]
 
 
 class ServerConfig(C.Structure):
@@ -140,6 +142,7 @@ def lib():
         L.hpmocd_graph_destroy.argtypes = [vp]
         L.hpmocd_graph_destroy.restype = None
         L.hpmocd_graph_info.argtypes = [vp, i32p, i64p, i32p]
+        L.hpmocd_graph_hash.argtypes = [vp, C.POINTER(C.c_uint64)]
         L.hpmocd_workspace_size.argtypes = [vp, C.POINTER(Params), C.POINTER(C.c_size_t)]
         L.hpmocd_run.argtypes = [vp, C.POINTER(Params), vp, C.c_size_t, vp,
                                  C.POINTER(C.POINTER(_Front))]
@@ -231,6 +234,9 @@ class Graph:
         _check(lib().hpmocd_graph_info(self._h, C.byref(n), C.byref(arcs), C.byref(md)),
                "hpmocd_graph_info")
         self.n, self.arcs, self.max_deg = n.value, arcs.value, md.value
+        h = C.c_uint64()
+        _check(lib().hpmocd_graph_hash(self._h, C.byref(h)), "hpmocd_graph_hash")
+        self.hash = h.value
 
     @property
     def handle(self):
@@ -347,6 +353,8 @@ class Snapshot:
     labels: np.ndarray   # (pop, n) int32, selection order
     A: np.ndarray
     S: np.ndarray
+    params: Params | None = None   # the run's parameters (checked on resume)
+    graph_hash: int = 0            # fingerprint of the run's graph (checked on resume)
 
 
 def run_to(graph: Graph, params: Params | None = None, *, stop_gen: int, stream=None,
@@ -365,7 +373,9 @@ def run_to(graph: Graph, params: Params | None = None, *, stop_gen: int, stream=
     sn = out.contents
     res = Snapshot(sn.g, np.ctypeslib.as_array(sn.labels, shape=(sn.pop_size, sn.n_nodes)).copy(),
                    np.ctypeslib.as_array(sn.A, shape=(sn.pop_size,)).copy(),
-                   np.ctypeslib.as_array(sn.S, shape=(sn.pop_size,)).copy())
+                   np.ctypeslib.as_array(sn.S, shape=(sn.pop_size,)).copy(),
+                   Params(*[getattr(sn.params, f) for f, _ in Params._fields_]),
+                   int(sn.graph_hash))
     lib().hpmocd_snapshot_free(out)
     return res
 
@@ -381,7 +391,9 @@ def resume(graph: Graph, snapshot: Snapshot, params: Params | None = None, *, st
     S = np.ascontiguousarray(snapshot.S, dtype=np.int64)
     sn = _Snapshot(snapshot.g, labels.shape[0], labels.shape[1],
                    labels.ctypes.data_as(C.POINTER(C.c_int32)),
-                   A.ctypes.data_as(C.POINTER(C.c_int64)), S.ctypes.data_as(C.POINTER(C.c_int64)))
+                   A.ctypes.data_as(C.POINTER(C.c_int64)), S.ctypes.data_as(C.POINTER(C.c_int64)),
+                   snapshot.params if snapshot.params is not None else Params(),
+                   snapshot.graph_hash)
     nbytes = workspace_size(graph, params)
     ws = workspace if workspace is not None else torch.empty(nbytes, dtype=torch.uint8,
                                                              device="cuda")

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <new>
 #include <vector>
 
@@ -84,6 +85,17 @@ int prepare_graph(int32_t n, const int32_t *row_ptr, const int32_t *col, HostGra
         h.class_end[k] = e;
     }
     h.large_max_deg = h.large.empty() ? 0 : row_ptr[h.large[0] + 1] - row_ptr[h.large[0]];
+    // fingerprint: FNV-1a (Fowler, Noll, Vo), 64-bit, over the bytes of n, row_ptr and the
+    // sorted col
+    uint64_t x = 0xcbf29ce484222325ull;
+    auto mix = [&x](const void *data, size_t bytes) {
+        const unsigned char *b = (const unsigned char *)data;
+        for (size_t i = 0; i < bytes; ++i) x = (x ^ b[i]) * 0x100000001b3ull;
+    };
+    mix(&n, sizeof(n));
+    mix(h.rp.data(), sizeof(int32_t) * h.rp.size());
+    mix(h.col.data(), sizeof(int32_t) * h.col.size());
+    h.hash = x;
     return HPMOCD_OK;
 }
 
@@ -97,7 +109,15 @@ size_t graph_block_bytes(int32_t n, int64_t m2, int32_t n_small, int32_t n_large
            al256(4 * std::max<size_t>(1, (size_t)n_large));
 }
 
-int place_graph(const HostGraph &h, void *block, hipStream_t s, hpmocd_graph *g)
+const void *Pinned::stage(const void *src, size_t bytes)
+{
+    void *p = take(bytes);
+    if (!p) return src;
+    std::memcpy(p, src, bytes);
+    return p;
+}
+
+static void graph_fields(const HostGraph &h, hpmocd_graph *g)
 {
     g->n = h.n;
     g->m2 = h.m2;
@@ -106,34 +126,58 @@ int place_graph(const HostGraph &h, void *block, hipStream_t s, hpmocd_graph *g)
     g->n_large = (int32_t)h.large.size();
     for (int k = 0; k < N_DEG_CLASSES; ++k) g->class_end[k] = h.class_end[k];
     g->large_max_deg = h.large_max_deg;
+    g->hash = h.hash;
+}
+
+void place_graph_deferred(const HostGraph &h, void *block, hpmocd_graph *g, Pinned *stage,
+                          std::vector<PendingCopy> &copies)
+{
+    graph_fields(h, g);
+    (void)hipGetDevice(&g->device);
+    const size_t b_rp = 4 * ((size_t)h.n + 1), b_col = 4 * (size_t)h.m2;
+    const size_t b_small = 4 * std::max<size_t>(1, h.small.size());
+    const size_t b_large = 4 * std::max<size_t>(1, h.large.size());
+    char *p = (char *)block;
+    g->owns_device = false;
+    g->d_rp = (int32_t *)p;
+    p += al256(b_rp);
+    g->d_col = (int32_t *)p;
+    p += al256(b_col);
+    g->d_small = (int32_t *)p;
+    p += al256(b_small);
+    g->d_large = (int32_t *)p;
+    p += al256(b_large);
+    g->d_up_rp = (int32_t *)p;
+    p += al256(b_rp);
+    g->d_up_col = (int32_t *)p;
+    auto add = [&](void *dst, const void *src, size_t bytes) {
+        if (!bytes) return;
+        if (stage) src = stage->stage(src, bytes);
+        copies.push_back(PendingCopy{dst, src, bytes});
+    };
+    add(g->d_rp, h.rp.data(), b_rp);
+    add(g->d_col, h.col.data(), b_col);
+    add(g->d_up_rp, h.up_rp.data(), b_rp);
+    add(g->d_up_col, h.up_col.data(), 4 * h.up_col.size());
+    add(g->d_small, h.small.data(), 4 * h.small.size());
+    add(g->d_large, h.large.data(), 4 * h.large.size());
+}
+
+int place_graph(const HostGraph &h, void *block, hipStream_t s, hpmocd_graph *g, Pinned *stage)
+{
+    graph_fields(h, g);
     if (hipGetDevice(&g->device) != hipSuccess) return HPMOCD_ERR_HIP;
     const size_t b_rp = 4 * ((size_t)h.n + 1), b_col = 4 * (size_t)h.m2;
     const size_t b_up = 4 * std::max<size_t>(1, h.up_col.size());
     const size_t b_small = 4 * std::max<size_t>(1, h.small.size());
     const size_t b_large = 4 * std::max<size_t>(1, h.large.size());
     if (block) {
-        char *p = (char *)block;
-        g->owns_device = false;
-        g->d_rp = (int32_t *)p;
-        p += al256(b_rp);
-        g->d_col = (int32_t *)p;
-        p += al256(b_col);
-        g->d_small = (int32_t *)p;
-        p += al256(b_small);
-        g->d_large = (int32_t *)p;
-        p += al256(b_large);
-        g->d_up_rp = (int32_t *)p;
-        p += al256(b_rp);
-        g->d_up_col = (int32_t *)p;
-        bool ok = hipMemcpyAsync(g->d_rp, h.rp.data(), b_rp, hipMemcpyHostToDevice, s) == hipSuccess;
-        ok = ok && hipMemcpyAsync(g->d_col, h.col.data(), b_col, hipMemcpyHostToDevice, s) == hipSuccess;
-        ok = ok && hipMemcpyAsync(g->d_up_rp, h.up_rp.data(), b_rp, hipMemcpyHostToDevice, s) == hipSuccess;
-        ok = ok && hipMemcpyAsync(g->d_up_col, h.up_col.data(), 4 * h.up_col.size(), hipMemcpyHostToDevice, s) == hipSuccess;
-        if (ok && !h.small.empty())
-            ok = hipMemcpyAsync(g->d_small, h.small.data(), 4 * h.small.size(), hipMemcpyHostToDevice, s) == hipSuccess;
-        if (ok && !h.large.empty())
-            ok = hipMemcpyAsync(g->d_large, h.large.data(), 4 * h.large.size(), hipMemcpyHostToDevice, s) == hipSuccess;
-        return ok ? HPMOCD_OK : HPMOCD_ERR_HIP;
+        std::vector<PendingCopy> copies;
+        place_graph_deferred(h, block, g, stage, copies);
+        for (const PendingCopy &c : copies)
+            if (hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+                return HPMOCD_ERR_HIP;
+        return HPMOCD_OK;
     }
     g->owns_device = true;
     bool ok = hipMalloc(&g->d_rp, b_rp) == hipSuccess;
@@ -257,6 +301,13 @@ void hpmocd_graph_destroy(hpmocd_graph *g)
     if (g->d_up_rp) (void)hipFree(g->d_up_rp);
     if (g->d_up_col) (void)hipFree(g->d_up_col);
     delete g;
+}
+
+int hpmocd_graph_hash(const hpmocd_graph *g, uint64_t *hash)
+{
+    if (!g || !hash) return HPMOCD_ERR_ARG;
+    *hash = g->hash;
+    return HPMOCD_OK;
 }
 
 int hpmocd_graph_info(const hpmocd_graph *g, int32_t *n, int64_t *arcs, int32_t *max_deg)

@@ -146,9 +146,11 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t s);
 int32_t kind_aux(Kind k, const Item &it);     // template / size argument of the kind
 hipError_t launch_kind(Kind k, const Span &sp, int32_t blocks, size_t lds, int32_t aux,
                        hipStream_t s);
+// k_dev (may be null): a device count; rows at or beyond it are skipped (k is then an upper
+// bound that sizes the launch)
 hipError_t launch_extract(int32_t n, int32_t ld, int32_t pop, const int32_t *pool,
                           const int32_t *q, const int32_t *ids, int32_t k, int32_t *out,
-                          hipStream_t s);
+                          hipStream_t s, const int32_t *k_dev = nullptr);
 // bad (may be null): a device flag set to 1 if a label lies outside [0, n); such labels are
 // stored as 0
 hipError_t launch_transpose_in(const int32_t *rows, int32_t n, int32_t n_ind, int32_t ld,

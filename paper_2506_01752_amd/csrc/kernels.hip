@@ -1543,9 +1543,10 @@ __global__ __launch_bounds__(128) void k_mutate_large(Span sp, int pmax)
 // ---------------------------------------------------------------------------------------
 __global__ void k_extract(int32_t n, int32_t ld, int32_t pop, const int32_t *__restrict__ pool,
                           const int32_t *__restrict__ q, const int32_t *__restrict__ ids,
-                          int32_t k, int32_t *__restrict__ out)
+                          int32_t k, const int32_t *__restrict__ k_dev, int32_t *__restrict__ out)
 {
     const int row = blockIdx.y;
+    if (k_dev && row >= *k_dev) return;  // rows beyond the device-side count hold nothing
     const int id = ids[row];
     const int32_t *src = id < pop ? pool + id : q + (id - pop);
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
@@ -1555,12 +1556,12 @@ __global__ void k_extract(int32_t n, int32_t ld, int32_t pop, const int32_t *__r
 
 hipError_t launch_extract(int32_t n, int32_t ld, int32_t pop, const int32_t *pool,
                           const int32_t *q, const int32_t *ids, int32_t k, int32_t *out,
-                          hipStream_t s)
+                          hipStream_t s, const int32_t *k_dev)
 {
     if (k == 0) return hipSuccess;
     unsigned bx = (unsigned)((n + 255) / 256);
     if (bx > 1024) bx = 1024;
-    k_extract<<<dim3(bx, (unsigned)k), 256, 0, s>>>(n, ld, pop, pool, q, ids, k, out);
+    k_extract<<<dim3(bx, (unsigned)k), 256, 0, s>>>(n, ld, pop, pool, q, ids, k, k_dev, out);
     return hipGetLastError();
 }
 

@@ -181,7 +181,8 @@ size_t meta_bytes(int32_t count)
            align_up(sizeof(int32_t) * (size_t)N_KINDS * ((size_t)count + 1));
 }
 
-int Meta::upload(const Item *host_items, int32_t n_items, void *region, hipStream_t s)
+int Meta::upload(const Item *host_items, int32_t n_items, void *region, hipStream_t s,
+                 Pinned *stage)
 {
     count = n_items;
     items = (Item *)region;
@@ -212,8 +213,13 @@ int Meta::upload(const Item *host_items, int32_t n_items, void *region, hipStrea
         if (acc > 0x7fffffff) return HPMOCD_ERR_ARG;
         totals[k] = (int32_t)acc;
     }
-    HIP_TRY(hipMemcpyAsync(items, hi, sizeof(Item) * (size_t)count, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync(starts, st, sizeof(int32_t) * n_starts, hipMemcpyHostToDevice, s));
+    const void *src_items = hi, *src_starts = st;
+    if (stage) {
+        src_items = stage->stage(hi, sizeof(Item) * (size_t)count);
+        src_starts = stage->stage(st, sizeof(int32_t) * n_starts);
+    }
+    HIP_TRY(hipMemcpyAsync(items, src_items, sizeof(Item) * (size_t)count, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(starts, src_starts, sizeof(int32_t) * n_starts, hipMemcpyHostToDevice, s));
     return HPMOCD_OK;
 }
 
@@ -404,7 +410,7 @@ int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, voi
 }
 
 // Front of one population after its final ranking (k_final has run): device -> host.
-int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out)
+int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out, Pinned *stage)
 {
     const RunLayout &L = P.L;
     const int32_t n = P.G->n, pop = P.c.pop;
@@ -428,7 +434,13 @@ int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out)
         hpmocd_front_free(f);
         return HPMOCD_ERR_NOMEM;
     }
-    bool ok = hipMemcpyAsync(f->labels, L.C, sizeof(int32_t) * (size_t)k * n, hipMemcpyDeviceToHost, s) == hipSuccess;
+    const size_t lab_bytes = sizeof(int32_t) * (size_t)k * n;
+    void *lab_dst = f->labels;
+    if (stage) {
+        stage->used = 0;
+        if (void *q = stage->take(lab_bytes)) lab_dst = q;
+    }
+    bool ok = hipMemcpyAsync(lab_dst, L.C, lab_bytes, hipMemcpyDeviceToHost, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(f->intra_arcs, L.st.fr_A, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(f->sum_deg_sq, L.st.fr_S, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(f->f1, L.st.fr_f1, sizeof(double) * k, hipMemcpyDeviceToHost, s) == hipSuccess;
@@ -438,7 +450,64 @@ int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out)
         hpmocd_front_free(f);
         return HPMOCD_ERR_HIP;
     }
+    if (lab_dst != f->labels) std::memcpy(f->labels, lab_dst, lab_bytes);
     f->selected = ks[1];
+    *out = f;
+    return HPMOCD_OK;
+}
+
+bool enqueue_front(const Pop &P, hipStream_t s, Pinned *stage, StagedFront *sf, hipError_t *err)
+{
+    const RunLayout &L = P.L;
+    const int32_t n = P.G->n, pop = P.c.pop;
+    const size_t lab = sizeof(int32_t) * (size_t)pop * n;
+    const size_t need = 256 + (lab + 255) / 256 * 256 + 4 * ((8 * (size_t)pop + 255) / 256 * 256);
+    *err = hipSuccess;
+    if (!stage || stage->used + need > stage->size) return false;
+    sf->ks = (int32_t *)stage->take(2 * sizeof(int32_t));
+    sf->labels = (int32_t *)stage->take(lab);
+    sf->A = (int64_t *)stage->take(8 * (size_t)pop);
+    sf->S = (int64_t *)stage->take(8 * (size_t)pop);
+    sf->f1 = (double *)stage->take(8 * (size_t)pop);
+    sf->f2 = (double *)stage->take(8 * (size_t)pop);
+    const hipMemcpyKind d2h = hipMemcpyDeviceToHost;
+    hipError_t e = launch_extract(n, P.c.ld, pop, L.pool[P.cur], L.q[P.cur], L.st.fr_id, pop, L.C,
+                                  s, L.st.fr_count);
+    if (e == hipSuccess) e = hipMemcpyAsync(sf->ks, L.st.fr_count, sizeof(int32_t), d2h, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sf->ks + 1, L.st.fr_sel, sizeof(int32_t), d2h, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sf->labels, L.C, lab, d2h, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sf->A, L.st.fr_A, 8 * (size_t)pop, d2h, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sf->S, L.st.fr_S, 8 * (size_t)pop, d2h, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sf->f1, L.st.fr_f1, 8 * (size_t)pop, d2h, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(sf->f2, L.st.fr_f2, 8 * (size_t)pop, d2h, s);
+    *err = e;
+    return true;
+}
+
+int front_from_staged(const Pop &P, const StagedFront &sf, hpmocd_front **out)
+{
+    const int32_t n = P.G->n, pop = P.c.pop;
+    const int32_t k = sf.ks[0], sel = sf.ks[1];
+    if (k < 1 || k > pop || sel < 0 || sel >= k) return HPMOCD_ERR_HIP;
+    hpmocd_front *f = (hpmocd_front *)std::calloc(1, sizeof(hpmocd_front));
+    if (!f) return HPMOCD_ERR_NOMEM;
+    f->n_solutions = k;
+    f->n_nodes = n;
+    f->labels = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)k * n);
+    f->intra_arcs = (int64_t *)std::malloc(sizeof(int64_t) * k);
+    f->sum_deg_sq = (int64_t *)std::malloc(sizeof(int64_t) * k);
+    f->f1 = (double *)std::malloc(sizeof(double) * k);
+    f->f2 = (double *)std::malloc(sizeof(double) * k);
+    if (!f->labels || !f->intra_arcs || !f->sum_deg_sq || !f->f1 || !f->f2) {
+        hpmocd_front_free(f);
+        return HPMOCD_ERR_NOMEM;
+    }
+    std::memcpy(f->labels, sf.labels, sizeof(int32_t) * (size_t)k * n);
+    std::memcpy(f->intra_arcs, sf.A, sizeof(int64_t) * k);
+    std::memcpy(f->sum_deg_sq, sf.S, sizeof(int64_t) * k);
+    std::memcpy(f->f1, sf.f1, sizeof(double) * k);
+    std::memcpy(f->f2, sf.f2, sizeof(double) * k);
+    f->selected = sel;
     *out = f;
     return HPMOCD_OK;
 }
@@ -845,6 +914,8 @@ int hpmocd_run_to(const hpmocd_graph *G, const hpmocd_params *p, int32_t stop_ge
     sn->g = stop_gen;
     sn->pop_size = pop;
     sn->n_nodes = n;
+    sn->params = *p;
+    sn->graph_hash = G->hash;
     sn->labels = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)pop * n);
     sn->A = (int64_t *)std::malloc(sizeof(int64_t) * pop);
     sn->S = (int64_t *)std::malloc(sizeof(int64_t) * pop);
@@ -873,6 +944,12 @@ int hpmocd_resume(const hpmocd_graph *G, const hpmocd_params *p, const hpmocd_sn
     if (rc) return rc;
     const int32_t n = G->n, pop = p->pop_size, T = p->generations;
     if (sn->n_nodes != n || sn->pop_size != pop || sn->g < 0 || sn->g > T) return HPMOCD_ERR_ARG;
+    // the snapshot belongs to this graph and these parameters (the generation count may grow)
+    const hpmocd_params &q = sn->params;
+    if (sn->graph_hash != G->hash || q.pop_size != pop || q.seed != p->seed ||
+        q.crossover_p != p->crossover_p || q.mutation_p != p->mutation_p ||
+        q.parents_per_child != p->parents_per_child)
+        return HPMOCD_ERR_ARG;
     for (size_t i = 0; i < (size_t)pop * n; ++i)
         if (sn->labels[i] < 0 || sn->labels[i] >= n) return HPMOCD_ERR_RANGE;
     const int64_t m2 = G->m2;
@@ -901,6 +978,24 @@ int hpmocd_resume(const hpmocd_graph *G, const hpmocd_params *p, const hpmocd_sn
     HIP_TRY(launch_finalize(m2, pop, (const unsigned long long *)st.ps_A,
                             (const unsigned long long *)st.ps_S, st.ps_f1, st.ps_f2, s));
     HIP_TRY(hipMemcpyAsync(st.gen, &gen, sizeof(int32_t), h2d, s));
+    // re-evaluate the members with the fitness kernels (eq. objectives) through a one-item
+    // table in the init table's place (no initialisation runs on resume): the stored A and S
+    // must be those of the stored labels
+    {
+        Item ev = P.item(ITEM_PARITY0);
+        ev.lab = P.L.pool[0];
+        Meta mv;
+        if ((rc = mv.upload(&ev, 1, (void *)B.meta[0].items, s))) return rc;
+        HIP_TRY(mv.launch(K_CLEAR, s));
+        HIP_TRY(mv.one(ONE_ZERO_ACC, s));
+        HIP_TRY(launch_fitness_kinds(mv, s, nullptr));
+        std::vector<int64_t> A(pop), S(pop);
+        HIP_TRY(hipMemcpyAsync(A.data(), ev.fit_A, sizeof(int64_t) * pop, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(S.data(), ev.fit_S, sizeof(int64_t) * pop, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < pop; ++i)
+            if (A[i] != sn->A[i] || S[i] != sn->S[i]) return HPMOCD_ERR_ARG;
+    }
     HIP_TRY(B.meta[1].launch(K_CLEAR, s));  // the plain histogram plane starts at zero
     if ((rc = B.generations(sn->g + 1, T, s, s != nullptr, nullptr, nullptr, nullptr, false)))
         return rc;

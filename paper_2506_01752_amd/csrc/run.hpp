@@ -87,10 +87,13 @@ struct Meta {
     size_t lds[N_KINDS] = {};
     int32_t aux[N_KINDS] = {};
     Span span(Kind k) const { return Span{items, starts + (size_t)k * (count + 1), count}; }
-    int upload(const Item *host_items, int32_t n_items, void *region, hipStream_t s);
-    int upload(const std::vector<Item> &host_items, void *region, hipStream_t s)
+    // stage: optional page-locked staging for the two copies
+    int upload(const Item *host_items, int32_t n_items, void *region, hipStream_t s,
+               Pinned *stage = nullptr);
+    int upload(const std::vector<Item> &host_items, void *region, hipStream_t s,
+               Pinned *stage = nullptr)
     {
-        return upload(host_items.data(), (int32_t)host_items.size(), region, s);
+        return upload(host_items.data(), (int32_t)host_items.size(), region, s, stage);
     }
     hipError_t launch(Kind k, hipStream_t s) const;
     hipError_t one(OneKernel which, hipStream_t s) const;
@@ -127,7 +130,23 @@ hipError_t launch_init_seq(const Meta &m, hipStream_t s, const Fork *fk);
 hipError_t launch_generation(const Meta &m, hipStream_t s, const EventPair *ev, const Fork *fk);
 int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, void *user,
                bool with_labels);
-int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out);
+// stage: optional page-locked staging for the labels' device-to-host copy (reset by the
+// call, which synchronises s)
+int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out, Pinned *stage = nullptr);
+
+// The front of a ranked population without host synchronisation: every copy is enqueued on
+// s into page-locked host memory taken from `stage` (all N_p candidate rows, the device
+// count deciding how many are filled), so nothing waits on the host in the middle of the
+// stream. front_from_staged builds the front once s has passed that point. Returns false
+// (nothing enqueued) when the staging region lacks room.
+struct StagedFront {
+    int32_t *ks = nullptr;       // front size, Alg. 3's choice
+    int32_t *labels = nullptr;   // N_p x n
+    int64_t *A = nullptr, *S = nullptr;
+    double *f1 = nullptr, *f2 = nullptr;
+};
+bool enqueue_front(const Pop &P, hipStream_t s, Pinned *stage, StagedFront *sf, hipError_t *err);
+int front_from_staged(const Pop &P, const StagedFront &sf, hpmocd_front **out);
 
 // Fitness of n_ind device label rows with the eval workspace at ws (hpmocd_eval_workspace_size
 // bytes, contents on entry irrelevant); results to host arrays. No device or host allocation

@@ -33,6 +33,9 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+constexpr size_t SERVER_UPLOAD_STAGE = (size_t)128 << 20;  // per flight
+constexpr size_t SERVER_FRONT_STAGE = (size_t)256 << 20;  // per flight
+
 // First-fit allocator over [0, size) with coalescing of free neighbours.
 class Arena {
 public:
@@ -106,6 +109,7 @@ struct Flight {
     hipEvent_t done = nullptr;
     Meta m_init, m_gen, m_final;
     std::vector<Request *> admitted, finals, released;
+    std::vector<StagedFront> staged;  // per final: its front's copies (ks null: none enqueued)
 };
 
 struct hpmocd_server {
@@ -114,10 +118,15 @@ struct hpmocd_server {
     size_t table_bytes = 0;       // two sets of three item tables at the start of the arena
     hipStream_t stream = nullptr;
     hipStream_t copy_stream = nullptr;  // front extraction beside the next step
+    hipStream_t up_stream = nullptr;    // graph uploads beside the step in flight
+    hipEvent_t up_done[2] = {nullptr, nullptr};
     int device = 0;
     Tuning tuning;
     Fork fork;  // side streams of the mutation classes
     Flight flight[2];
+    // page-locked staging of each flight's step, free again once that step has completed:
+    // graph and table uploads, and the fronts of the requests it finishes
+    Pinned up_stage[2], front_stage[2];
     Clock::time_point epoch;
 
     std::mutex mu;
@@ -145,6 +154,11 @@ struct hpmocd_server {
         for (Flight &f : flight)
             if (f.done) (void)hipEventDestroy(f.done);
         if (copy_stream) (void)hipStreamDestroy(copy_stream);
+        if (up_stream) (void)hipStreamDestroy(up_stream);
+        for (hipEvent_t e : up_done)
+            if (e) (void)hipEventDestroy(e);
+        for (Pinned *p : {&up_stage[0], &up_stage[1], &front_stage[0], &front_stage[1]})
+            if (p->base) (void)hipHostFree(p->base);
     }
 };
 
@@ -176,7 +190,8 @@ static void drop_host_graph(Request *r) { r->hg = HostGraph(); }
 // FIFO baseline: the one resident request as a plain hipGraph-replayed run (synchronous).
 int hpmocd_server::run_fifo(Request *r)
 {
-    int rc = place_graph(r->hg, arena + r->off, stream, &r->graph);
+    up_stage[0].used = 0;  // the previous run drained the stream
+    int rc = place_graph(r->hg, arena + r->off, stream, &r->graph, &up_stage[0]);
     if (rc) return rc;
     const hpmocd_graph *gp = &r->graph;
     rc = run_batch(&gp, 1, &r->p, arena + r->off + r->graph_bytes, r->bytes - r->graph_bytes,
@@ -199,11 +214,26 @@ int hpmocd_server::launch(Flight &f, int set, std::vector<Request *> &admitted)
 {
     f.admitted = admitted;
     f.finals.clear();
+    f.staged.clear();
+    // this set's staging was last read by the step launched into it two steps ago, which
+    // has completed
+    Pinned *stage = &up_stage[set];
+    stage->used = 0;
+    // stage every new graph on the host first, then issue all their copies: the stream
+    // does not wait on host-side staging between copies
+    std::vector<PendingCopy> copies;
     for (Request *r : admitted) {
-        int rc = place_graph(r->hg, arena + r->off, stream, &r->graph);
-        if (rc) return rc;
+        place_graph_deferred(r->hg, arena + r->off, &r->graph, stage, copies);
         r->pop.setup(&r->graph, r->p, arena + r->off + r->graph_bytes, tuning, 1, false);
         r->fresh = true;
+    }
+    // the copies run on their own stream beside the step still in flight (the blocks of newly
+    // admitted requests are not used by it); this step's kernels wait for them
+    if (!copies.empty()) {
+        for (const PendingCopy &c : copies)
+            HIP_TRY(hipMemcpyAsync(c.dst, c.src, c.bytes, hipMemcpyHostToDevice, up_stream));
+        HIP_TRY(hipEventRecord(up_done[set], up_stream));
+        HIP_TRY(hipStreamWaitEvent(stream, up_done[set], 0));
     }
     int64_t nodes = 0;
     for (Request *r : active) nodes += r->graph.n;
@@ -220,12 +250,12 @@ int hpmocd_server::launch(Flight &f, int set, std::vector<Request *> &admitted)
     const size_t tb = align_up(meta_bytes(cfg.max_active));
     char *tables = arena + (size_t)set * 3 * tb;
     if (!init_items.empty()) {
-        int rc = f.m_init.upload(init_items, tables, stream);
+        int rc = f.m_init.upload(init_items, tables, stream, stage);
         if (rc) return rc;
         HIP_TRY(launch_init_seq(f.m_init, stream, &fork));
     }
     if (!gen_items.empty()) {
-        int rc = f.m_gen.upload(gen_items, tables + tb, stream);
+        int rc = f.m_gen.upload(gen_items, tables + tb, stream, stage);
         if (rc) return rc;
         HIP_TRY(launch_generation(f.m_gen, stream, nullptr, &fork));
         for (Request *r : gen_reqs) {
@@ -243,9 +273,20 @@ int hpmocd_server::launch(Flight &f, int set, std::vector<Request *> &admitted)
         }
     }
     if (!final_items.empty()) {
-        int rc = f.m_final.upload(final_items, tables + 2 * tb, stream);
+        int rc = f.m_final.upload(final_items, tables + 2 * tb, stream, stage);
         if (rc) return rc;
         HIP_TRY(f.m_final.one(ONE_FINAL, stream));
+        // the fronts' copies follow in the same stream, into page-locked memory, so that
+        // no host round trip interrupts the stream (fronts that do not fit are copied when
+        // the step completes)
+        front_stage[set].used = 0;
+        f.staged.assign(f.finals.size(), StagedFront{});
+        for (size_t i = 0; i < f.finals.size(); ++i) {
+            hipError_t e = hipSuccess;
+            if (!enqueue_front(f.finals[i]->pop, stream, &front_stage[set], &f.staged[i], &e))
+                f.staged[i] = StagedFront{};
+            if (e != hipSuccess) return HPMOCD_ERR_HIP;
+        }
         active.erase(std::remove_if(active.begin(), active.end(),
                                     [](Request *r) { return r->gens_done == r->p.generations; }),
                      active.end());
@@ -262,10 +303,14 @@ int hpmocd_server::complete(Flight &f)
 {
     HIP_TRY(hipEventSynchronize(f.done));
     for (Request *r : f.admitted) drop_host_graph(r);
-    for (Request *r : f.finals) {
-        int rc = extract_front(r->pop, copy_stream, &r->front);
+    for (size_t i = 0; i < f.finals.size(); ++i) {
+        Request *r = f.finals[i];
+        const bool staged = i < f.staged.size() && f.staged[i].ks;
+        int rc = staged ? front_from_staged(r->pop, f.staged[i], &r->front)
+                        : extract_front(r->pop, copy_stream, &r->front);
         if (rc) return rc;
     }
+    f.staged.clear();
     std::lock_guard<std::mutex> lk(mu);
     for (Request *r : f.finals) release(r, HPMOCD_OK);
     for (Request *r : f.released) release(r, HPMOCD_ERR_CANCELLED);
@@ -342,6 +387,7 @@ void hpmocd_server::run()
         cur ^= 1;
     }
     // shutdown or failure: settle what was launched, then nothing queued will run
+    (void)hipStreamSynchronize(up_stream);
     (void)hipStreamSynchronize(stream);
     (void)hipStreamSynchronize(copy_stream);
     std::lock_guard<std::mutex> lk(mu);
@@ -389,8 +435,18 @@ int hpmocd_server_create(const hpmocd_server_config *cfg, void *d_arena, size_t 
     s->epoch = Clock::now();
     bool ok = hipGetDevice(&s->device) == hipSuccess && s->fork.init() == HPMOCD_OK;
     ok = ok && hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&s->up_stream, hipStreamNonBlocking) == hipSuccess;
+    for (hipEvent_t &e : s->up_done)
+        ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     for (Flight &f : s->flight)
         ok = ok && hipEventCreateWithFlags(&f.done, hipEventDisableTiming) == hipSuccess;
+    // staging sizes: a step's new graphs and tables, and one front's labels; larger copies
+    // fall back to pageable memory
+    for (Pinned *p : {&s->up_stage[0], &s->up_stage[1], &s->front_stage[0], &s->front_stage[1]}) {
+        p->size = (p == &s->front_stage[0] || p == &s->front_stage[1]) ? SERVER_FRONT_STAGE
+                                                                       : SERVER_UPLOAD_STAGE;
+        ok = ok && hipHostMalloc((void **)&p->base, p->size, hipHostMallocDefault) == hipSuccess;
+    }
     if (!ok) {
         delete s;
         return HPMOCD_ERR_HIP;

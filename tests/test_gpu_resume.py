@@ -64,3 +64,43 @@ def test_resume_rejects_bad_snapshots(hp):
         hp.resume(dg, hp.Snapshot(9, snap.labels, snap.A, snap.S), p)  # g > T
     with pytest.raises(hp.HpmocdError):
         hp.run_to(dg, p, stop_gen=5)  # beyond T
+    assert snap.graph_hash == dg.hash and snap.params.seed == 1
+    # another seed, crossover or mutation rate, ensemble size: not this run's snapshot
+    for kw in (dict(seed=2), dict(crossover_p=0.8), dict(mutation_p=0.2),
+               dict(parents_per_child=3)):
+        with pytest.raises(hp.HpmocdError) as e:
+            hp.resume(dg, snap, hp.make_params(**dict(dict(pop_size=16, generations=4, seed=1),
+                                                      **kw)))
+        assert e.value.status == hp.ERR_ARG, kw
+    # another graph with the same number of nodes
+    other = synth.small_1k(seed=1)
+    assert other.n == g.n
+    dg2 = hp.Graph(other.row_ptr, other.col)
+    assert dg2.hash != dg.hash
+    with pytest.raises(hp.HpmocdError) as e:
+        hp.resume(dg2, snap, p)
+    assert e.value.status == hp.ERR_ARG
+    # objectives that do not belong to the labels (re-evaluated on the device)
+    for which in ("A", "S"):
+        stale = hp.Snapshot(snap.g, snap.labels, snap.A.copy(), snap.S.copy(), snap.params,
+                            snap.graph_hash)
+        getattr(stale, which)[7] += 2
+        with pytest.raises(hp.HpmocdError) as e:
+            hp.resume(dg, stale, p)
+        assert e.value.status == hp.ERR_ARG, which
+    # a snapshot without its fingerprint (e.g. built by hand) is refused
+    with pytest.raises(hp.HpmocdError):
+        hp.resume(dg, hp.Snapshot(snap.g, snap.labels, snap.A, snap.S), p)
+
+
+def test_resume_to_more_generations(hp):
+    """The generation count may grow on resume: a run stopped at k of T and resumed to T' > T
+    equals the uninterrupted run of T' generations."""
+    import torch
+    s = torch.cuda.Stream()
+    g = synth.small_1k()
+    dg = hp.Graph(g.row_ptr, g.col)
+    p6 = hp.make_params(pop_size=24, generations=6, seed=3)
+    p11 = hp.make_params(pop_size=24, generations=11, seed=3)
+    snap = hp.run_to(dg, p6, stop_gen=6, stream=s)
+    assert same(hp.resume(dg, snap, p11, stream=s), hp.run(dg, p11, stream=s))
