@@ -253,6 +253,9 @@ typedef struct {
     int32_t max_active;         /* 1 .. HPMOCD_SERVER_MAX_ACTIVE */
     int32_t parents_per_child;  /* E_S of every request */
     int32_t flags;              /* HPMOCD_SERVER_FIFO or 0 */
+    size_t host_stage_bytes;    /* page-locked host staging per in-flight step (a third for
+                                 * graph and table uploads, two thirds for fronts; copies that
+                                 * do not fit go from or to pageable memory); 0 = 384 MB */
 } hpmocd_server_config;
 
 /* Life of one request, seconds on the server's monotonic clock (0 = server creation). */

@@ -105,7 +105,8 @@ class _Snapshot(C.Structure):
 
 class ServerConfig(C.Structure):
     _fields_ = [("hbm_budget", C.c_size_t), ("max_active", C.c_int32),
-                ("parents_per_child", C.c_int32), ("flags", C.c_int32)]
+                ("parents_per_child", C.c_int32), ("flags", C.c_int32),
+                ("host_stage_bytes", C.c_size_t)]
 
 
 class RequestInfo(C.Structure):
@@ -495,13 +496,14 @@ class Server:
     is on the host (the GIL is released meanwhile)."""
 
     def __init__(self, hbm_budget: int, max_active: int = 256, parents_per_child: int = 4,
-                 fifo: bool = False, stream=None):
+                 fifo: bool = False, stream=None, host_stage_bytes: int = 0):
         import torch
         self._h = C.c_void_p()
         over = lib().hpmocd_server_arena_overhead(max_active)
         self.arena = torch.empty(over + hbm_budget, dtype=torch.uint8, device="cuda")
         self.stream = stream if stream is not None else torch.cuda.Stream()
-        cfg = ServerConfig(hbm_budget, max_active, parents_per_child, SERVER_FIFO if fifo else 0)
+        cfg = ServerConfig(hbm_budget, max_active, parents_per_child, SERVER_FIFO if fifo else 0,
+                           host_stage_bytes)
         _check(lib().hpmocd_server_create(C.byref(cfg), C.c_void_p(self.arena.data_ptr()),
                                           self.arena.numel(), C.c_void_p(self.stream.cuda_stream),
                                           C.byref(self._h)), "hpmocd_server_create")

@@ -33,8 +33,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
-constexpr size_t SERVER_UPLOAD_STAGE = (size_t)128 << 20;  // per flight
-constexpr size_t SERVER_FRONT_STAGE = (size_t)256 << 20;  // per flight
+constexpr size_t SERVER_STAGE_DEFAULT = (size_t)384 << 20;  // per flight
+constexpr size_t SERVER_STAGE_MIN = 4096;  // smaller regions are not allocated (no staging)
 
 // First-fit allocator over [0, size) with coalescing of free neighbours.
 class Arena {
@@ -440,11 +440,14 @@ int hpmocd_server_create(const hpmocd_server_config *cfg, void *d_arena, size_t 
         ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
     for (Flight &f : s->flight)
         ok = ok && hipEventCreateWithFlags(&f.done, hipEventDisableTiming) == hipSuccess;
-    // staging sizes: a step's new graphs and tables, and one front's labels; larger copies
-    // fall back to pageable memory
+    // staging per in-flight step: a third for the step's new graphs and tables, two thirds
+    // for the fronts it finishes; copies that do not fit use pageable memory
+    const size_t stage = cfg->host_stage_bytes ? cfg->host_stage_bytes : SERVER_STAGE_DEFAULT;
     for (Pinned *p : {&s->up_stage[0], &s->up_stage[1], &s->front_stage[0], &s->front_stage[1]}) {
-        p->size = (p == &s->front_stage[0] || p == &s->front_stage[1]) ? SERVER_FRONT_STAGE
-                                                                       : SERVER_UPLOAD_STAGE;
+        const bool front = p == &s->front_stage[0] || p == &s->front_stage[1];
+        const size_t bytes = (front ? 2 * (stage / 3) : stage / 3) / 256 * 256;
+        if (bytes < SERVER_STAGE_MIN) continue;
+        p->size = bytes;
         ok = ok && hipHostMalloc((void **)&p->base, p->size, hipHostMallocDefault) == hipSuccess;
     }
     if (!ok) {

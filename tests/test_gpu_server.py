@@ -52,14 +52,18 @@ def alone(hp, g, kw, stream):
     return hp.run(hp.Graph(g.row_ptr, g.col), stream=stream, **kw)
 
 
-def test_server_mix_equals_alone(hp):
+@pytest.mark.parametrize("stage", [0, 300_000, 1])
+def test_server_mix_equals_alone(hp, stage):
+    """stage: page-locked host staging per in-flight step (0: the default, ample; 300 KB:
+    small graphs and fronts staged, larger ones copied from and to pageable memory; 1: none,
+    every copy pageable and every front extracted when its step completes)."""
     import torch
     reqs = mixed_requests(14, seed=4) + [(synth.fig1_graph(), dict(pop_size=16, generations=5,
                                                                     seed=3)),
                                          (synth.star(50), dict(pop_size=20, generations=7,
                                                                seed=2))]
     print(f"{len(reqs)} requests, n = {[g.n for g, _ in reqs]}", flush=True)
-    srv = hp.Server(hbm_budget=2 << 30, max_active=64)
+    srv = hp.Server(hbm_budget=2 << 30, max_active=64, host_stage_bytes=stage)
     tickets = []
     rng = np.random.default_rng(0)
     for g, kw in reqs:  # staggered arrivals: requests join runs already in progress
