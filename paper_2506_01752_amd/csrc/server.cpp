@@ -33,6 +33,10 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// Steps in flight: the scheduler launches a step, then waits for the oldest of the others and
+// settles it (fronts to the host, memory released), so host work of up to SERVER_DEPTH - 1
+// steps' length can pass without the device waiting for the next launch.
+constexpr int SERVER_DEPTH = 3;
 constexpr size_t SERVER_STAGE_DEFAULT = (size_t)384 << 20;  // per flight
 constexpr size_t SERVER_STAGE_MIN = 4096;  // smaller regions are not allocated (no staging)
 
@@ -115,18 +119,18 @@ struct Flight {
 struct hpmocd_server {
     hpmocd_server_config cfg{};
     char *arena = nullptr;        // caller's device memory
-    size_t table_bytes = 0;       // two sets of three item tables at the start of the arena
+    size_t table_bytes = 0;       // SERVER_DEPTH sets of three item tables at the arena's start
     hipStream_t stream = nullptr;
     hipStream_t copy_stream = nullptr;  // front extraction beside the next step
     hipStream_t up_stream = nullptr;    // graph uploads beside the step in flight
-    hipEvent_t up_done[2] = {nullptr, nullptr};
+    hipEvent_t up_done[SERVER_DEPTH] = {};
     int device = 0;
     Tuning tuning;
     Fork fork;  // side streams of the mutation classes
-    Flight flight[2];
+    Flight flight[SERVER_DEPTH];
     // page-locked staging of each flight's step, free again once that step has completed:
     // graph and table uploads, and the fronts of the requests it finishes
-    Pinned up_stage[2], front_stage[2];
+    Pinned up_stage[SERVER_DEPTH], front_stage[SERVER_DEPTH];
     Clock::time_point epoch;
 
     std::mutex mu;
@@ -157,14 +161,15 @@ struct hpmocd_server {
         if (up_stream) (void)hipStreamDestroy(up_stream);
         for (hipEvent_t e : up_done)
             if (e) (void)hipEventDestroy(e);
-        for (Pinned *p : {&up_stage[0], &up_stage[1], &front_stage[0], &front_stage[1]})
-            if (p->base) (void)hipHostFree(p->base);
+        for (int i = 0; i < SERVER_DEPTH; ++i)
+            for (Pinned *p : {&up_stage[i], &front_stage[i]})
+                if (p->base) (void)hipHostFree(p->base);
     }
 };
 
 size_t hpmocd_server_arena_overhead(int32_t max_active)
 {
-    return 6 * align_up(meta_bytes(std::max(1, max_active)));
+    return 3 * SERVER_DEPTH * align_up(meta_bytes(std::max(1, max_active)));
 }
 
 void hpmocd_server::finish(Request *r, int st)
@@ -215,8 +220,8 @@ int hpmocd_server::launch(Flight &f, int set, std::vector<Request *> &admitted)
     f.admitted = admitted;
     f.finals.clear();
     f.staged.clear();
-    // this set's staging was last read by the step launched into it two steps ago, which
-    // has completed
+    // this set's staging was last read by the step launched into it SERVER_DEPTH steps ago,
+    // which has completed
     Pinned *stage = &up_stage[set];
     stage->used = 0;
     // stage every new graph on the host first, then issue all their copies: the stream
@@ -329,21 +334,29 @@ void hpmocd_server::run()
         broken = HPMOCD_ERR_HIP;
     }
     const bool fifo = (cfg.flags & HPMOCD_SERVER_FIFO) != 0;
-    int cur = 0;  // flight[cur] takes the next launch; flight[cur ^ 1] is the one in flight
+    // flight[cur] takes the next launch; flight[(cur + 1) % SERVER_DEPTH] is the oldest in
+    // flight, flight[(cur + SERVER_DEPTH - 1) % SERVER_DEPTH] the newest
+    int cur = 0;
+    auto any_in_flight = [&] {
+        for (const Flight &f : flight)
+            if (f.valid) return true;
+        return false;
+    };
     for (;;) {
         std::vector<Request *> admitted;
         {
             std::unique_lock<std::mutex> lk(mu);
             cv_work.wait(lk, [&] {
-                return stop || !queue.empty() || !active.empty() || flight[cur ^ 1].valid;
+                return stop || !queue.empty() || !active.empty() || any_in_flight();
             });
             if (stop || broken) break;
-            // resident requests cancelled since the last launch: the step in flight may still
-            // use their memory, so it is released when that step completes
+            // resident requests cancelled since the last launch: the steps in flight may still
+            // use their memory, so it is released when the newest of them completes
+            Flight &newest = flight[(cur + SERVER_DEPTH - 1) % SERVER_DEPTH];
             for (Request *r : active)
                 if (r->cancel) {
-                    if (flight[cur ^ 1].valid)
-                        flight[cur ^ 1].released.push_back(r);
+                    if (newest.valid)
+                        newest.released.push_back(r);
                     else
                         release(r, HPMOCD_ERR_CANCELLED);
                 }
@@ -376,7 +389,8 @@ void hpmocd_server::run()
             rc = fifo ? run_fifo(active.front()) : launch(flight[cur], cur, admitted);
             launched = true;
         }
-        if (!rc && flight[cur ^ 1].valid) rc = complete(flight[cur ^ 1]);
+        Flight &oldest = flight[(cur + 1) % SERVER_DEPTH];
+        if (!rc && oldest.valid) rc = complete(oldest);
         std::lock_guard<std::mutex> lk(mu);
         stats.busy_s += now() - t0;
         if (launched) ++stats.steps;
@@ -384,7 +398,7 @@ void hpmocd_server::run()
             broken = rc;
             break;
         }
-        cur ^= 1;
+        cur = (cur + 1) % SERVER_DEPTH;
     }
     // shutdown or failure: settle what was launched, then nothing queued will run
     (void)hipStreamSynchronize(up_stream);
@@ -443,13 +457,14 @@ int hpmocd_server_create(const hpmocd_server_config *cfg, void *d_arena, size_t 
     // staging per in-flight step: a third for the step's new graphs and tables, two thirds
     // for the fronts it finishes; copies that do not fit use pageable memory
     const size_t stage = cfg->host_stage_bytes ? cfg->host_stage_bytes : SERVER_STAGE_DEFAULT;
-    for (Pinned *p : {&s->up_stage[0], &s->up_stage[1], &s->front_stage[0], &s->front_stage[1]}) {
-        const bool front = p == &s->front_stage[0] || p == &s->front_stage[1];
-        const size_t bytes = (front ? 2 * (stage / 3) : stage / 3) / 256 * 256;
-        if (bytes < SERVER_STAGE_MIN) continue;
-        p->size = bytes;
-        ok = ok && hipHostMalloc((void **)&p->base, p->size, hipHostMallocDefault) == hipSuccess;
-    }
+    for (int i = 0; i < SERVER_DEPTH; ++i)
+        for (Pinned *p : {&s->up_stage[i], &s->front_stage[i]}) {
+            const bool front = p == &s->front_stage[i];
+            const size_t bytes = (front ? 2 * (stage / 3) : stage / 3) / 256 * 256;
+            if (bytes < SERVER_STAGE_MIN) continue;
+            p->size = bytes;
+            ok = ok && hipHostMalloc((void **)&p->base, p->size, hipHostMallocDefault) == hipSuccess;
+        }
     if (!ok) {
         delete s;
         return HPMOCD_ERR_HIP;
