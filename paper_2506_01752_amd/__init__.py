@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import weakref
 from dataclasses import dataclass
 
 import numpy as np
@@ -295,16 +296,27 @@ def _stream_handle(stream):
     return C.c_void_p(s.cuda_stream)
 
 
+def _free_front(ptr):
+    try:
+        lib().hpmocd_front_free(ptr)
+    except Exception:  # pragma: no cover - interpreter shutdown
+        pass
+
+
 def _front_from(ptr) -> Front:
+    """The library's front as numpy arrays. The label matrix (k x n int32, hundreds of MB on
+    large graphs) is not copied: the array views the library's memory, which is released
+    when the array (and every view of it) is gone."""
     f = ptr.contents
     k, n = f.n_solutions, f.n_nodes
-    out = Front(np.ctypeslib.as_array(f.labels, shape=(k, n)).copy(),
-                np.ctypeslib.as_array(f.intra_arcs, shape=(k,)).copy(),
-                np.ctypeslib.as_array(f.sum_deg_sq, shape=(k,)).copy(),
-                np.ctypeslib.as_array(f.f1, shape=(k,)).copy(),
-                np.ctypeslib.as_array(f.f2, shape=(k,)).copy(), f.selected)
-    lib().hpmocd_front_free(ptr)
-    return out
+    buf = (C.c_int32 * (k * n)).from_address(C.addressof(f.labels.contents))
+    labels = np.frombuffer(buf, dtype=np.int32).reshape(k, n)
+    weakref.finalize(buf, _free_front, ptr)
+    return Front(labels,
+                 np.ctypeslib.as_array(f.intra_arcs, shape=(k,)).copy(),
+                 np.ctypeslib.as_array(f.sum_deg_sq, shape=(k,)).copy(),
+                 np.ctypeslib.as_array(f.f1, shape=(k,)).copy(),
+                 np.ctypeslib.as_array(f.f2, shape=(k,)).copy(), f.selected)
 
 
 def run(graph: Graph, params: Params | None = None, *, stream=None, workspace=None, flags=0,

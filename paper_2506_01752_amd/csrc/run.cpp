@@ -8,7 +8,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <vector>
+
+#include <sys/mman.h>
 
 #include "host.hpp"
 #include "philox.hpp"
@@ -410,6 +413,94 @@ int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, voi
 }
 
 // Front of one population after its final ranking (k_final has run): device -> host.
+namespace {
+
+// Device-to-host copies of large results (a front's labels: up to N_p x n int32, 400 MB at
+// |V| = 1M, pop 100). From pageable memory the runtime stages such a copy through small
+// buffers of its own at a few GB/s; here it goes through two 16 MB page-locked buffers per
+// device (allocated on first use, kept until the process ends): the DMA of one chunk runs
+// while the previous chunk is copied out on the host. Calls from several threads take turns.
+constexpr size_t BOUNCE_CHUNK = (size_t)16 << 20;
+constexpr size_t BOUNCE_MIN = (size_t)4 << 20;  // smaller copies go direct
+constexpr int BOUNCE_DEVICES = 64;
+struct Bounce {
+    std::mutex mu;
+    bool tried = false;
+    char *buf[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+};
+Bounce g_bounce[BOUNCE_DEVICES];
+
+// copies bytes from device memory src to host memory dst in stream order on s and returns
+// with the copy complete
+hipError_t copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    Bounce *b = (dev >= 0 && dev < BOUNCE_DEVICES && bytes >= BOUNCE_MIN) ? &g_bounce[dev] : nullptr;
+    std::unique_lock<std::mutex> lock;
+    if (b) {
+        lock = std::unique_lock<std::mutex>(b->mu);
+        if (!b->tried) {
+            b->tried = true;
+            bool ok = true;
+            for (int i = 0; i < 2; ++i) {
+                ok = ok && hipHostMalloc((void **)&b->buf[i], BOUNCE_CHUNK, hipHostMallocDefault) == hipSuccess;
+                ok = ok && hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) == hipSuccess;
+            }
+            if (!ok) {
+                for (int i = 0; i < 2; ++i) {
+                    if (b->buf[i]) (void)hipHostFree(b->buf[i]);
+                    if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
+                    b->buf[i] = nullptr;
+                    b->ev[i] = nullptr;
+                }
+            }
+        }
+        if (!b->buf[0]) b = nullptr;
+    }
+    if (!b) {
+        if ((e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+        return hipStreamSynchronize(s);
+    }
+    const size_t nchunk = (bytes + BOUNCE_CHUNK - 1) / BOUNCE_CHUNK;
+    for (size_t i = 0; i <= nchunk; ++i) {
+        if (i < nchunk) {  // chunk i into buffer i % 2 (its previous chunk was copied out)
+            const size_t off = i * BOUNCE_CHUNK, len = std::min(BOUNCE_CHUNK, bytes - off);
+            e = hipMemcpyAsync(b->buf[i & 1], (const char *)src + off, len, hipMemcpyDeviceToHost, s);
+            if (e == hipSuccess) e = hipEventRecord(b->ev[i & 1], s);
+            if (e != hipSuccess) {
+                (void)hipStreamSynchronize(s);
+                return e;
+            }
+        }
+        if (i > 0) {  // chunk i - 1 out of its buffer while chunk i is in flight
+            const size_t j = i - 1, off = j * BOUNCE_CHUNK, len = std::min(BOUNCE_CHUNK, bytes - off);
+            if ((e = hipEventSynchronize(b->ev[j & 1])) != hipSuccess) {
+                (void)hipStreamSynchronize(s);
+                return e;
+            }
+            std::memcpy((char *)dst + off, b->buf[j & 1], len);
+        }
+    }
+    return hipSuccess;
+}
+
+// host memory for a front's labels: 2 MB-aligned, with transparent huge pages requested, so
+// that filling hundreds of megabytes does not fault on every 4 KB page; freed by free()
+void *alloc_labels(size_t bytes)
+{
+    constexpr size_t HUGE_PAGE = (size_t)2 << 20;
+    if (bytes < HUGE_PAGE) return std::malloc(bytes ? bytes : 1);
+    const size_t rounded = (bytes + HUGE_PAGE - 1) / HUGE_PAGE * HUGE_PAGE;
+    void *p = std::aligned_alloc(HUGE_PAGE, rounded);
+    if (p) (void)madvise(p, rounded, MADV_HUGEPAGE);
+    return p;
+}
+
+}  // namespace
+
 int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out, Pinned *stage)
 {
     const RunLayout &L = P.L;
@@ -425,7 +516,8 @@ int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out, Pinned *stage
     if (!f) return HPMOCD_ERR_NOMEM;
     f->n_solutions = k;
     f->n_nodes = n;
-    f->labels = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)k * n);
+    const size_t lab_bytes = sizeof(int32_t) * (size_t)k * n;
+    f->labels = (int32_t *)alloc_labels(lab_bytes);
     f->intra_arcs = (int64_t *)std::malloc(sizeof(int64_t) * k);
     f->sum_deg_sq = (int64_t *)std::malloc(sizeof(int64_t) * k);
     f->f1 = (double *)std::malloc(sizeof(double) * k);
@@ -434,23 +526,27 @@ int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out, Pinned *stage
         hpmocd_front_free(f);
         return HPMOCD_ERR_NOMEM;
     }
-    const size_t lab_bytes = sizeof(int32_t) * (size_t)k * n;
     void *lab_dst = f->labels;
     if (stage) {
         stage->used = 0;
         if (void *q = stage->take(lab_bytes)) lab_dst = q;
     }
-    bool ok = hipMemcpyAsync(lab_dst, L.C, lab_bytes, hipMemcpyDeviceToHost, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(f->intra_arcs, L.st.fr_A, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s) == hipSuccess;
+    bool ok = hipMemcpyAsync(f->intra_arcs, L.st.fr_A, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(f->sum_deg_sq, L.st.fr_S, sizeof(int64_t) * k, hipMemcpyDeviceToHost, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(f->f1, L.st.fr_f1, sizeof(double) * k, hipMemcpyDeviceToHost, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(f->f2, L.st.fr_f2, sizeof(double) * k, hipMemcpyDeviceToHost, s) == hipSuccess;
+    if (lab_dst != f->labels) {  // into the caller's page-locked staging, then out of it
+        ok = ok && hipMemcpyAsync(lab_dst, L.C, lab_bytes, hipMemcpyDeviceToHost, s) == hipSuccess;
+        ok = ok && hipStreamSynchronize(s) == hipSuccess;
+        if (ok) std::memcpy(f->labels, lab_dst, lab_bytes);
+    } else {
+        ok = ok && copy_to_host(f->labels, L.C, lab_bytes, s) == hipSuccess;
+    }
     ok = ok && hipStreamSynchronize(s) == hipSuccess;
     if (!ok) {
         hpmocd_front_free(f);
         return HPMOCD_ERR_HIP;
     }
-    if (lab_dst != f->labels) std::memcpy(f->labels, lab_dst, lab_bytes);
     f->selected = ks[1];
     *out = f;
     return HPMOCD_OK;
@@ -493,7 +589,7 @@ int front_from_staged(const Pop &P, const StagedFront &sf, hpmocd_front **out)
     if (!f) return HPMOCD_ERR_NOMEM;
     f->n_solutions = k;
     f->n_nodes = n;
-    f->labels = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)k * n);
+    f->labels = (int32_t *)alloc_labels(sizeof(int32_t) * (size_t)k * n);
     f->intra_arcs = (int64_t *)std::malloc(sizeof(int64_t) * k);
     f->sum_deg_sq = (int64_t *)std::malloc(sizeof(int64_t) * k);
     f->f1 = (double *)std::malloc(sizeof(double) * k);
@@ -924,7 +1020,7 @@ int hpmocd_run_to(const hpmocd_graph *G, const hpmocd_params *p, int32_t stop_ge
         return HPMOCD_ERR_NOMEM;
     }
     const hipMemcpyKind d2h = hipMemcpyDeviceToHost;
-    bool ok = hipMemcpyAsync(sn->labels, P.L.C, sizeof(int32_t) * (size_t)pop * n, d2h, s) == hipSuccess;
+    bool ok = copy_to_host(sn->labels, P.L.C, sizeof(int32_t) * (size_t)pop * n, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(sn->A, P.L.st.ps_A, sizeof(int64_t) * pop, d2h, s) == hipSuccess;
     ok = ok && hipMemcpyAsync(sn->S, P.L.st.ps_S, sizeof(int64_t) * pop, d2h, s) == hipSuccess;
     ok = ok && hipStreamSynchronize(s) == hipSuccess;
