@@ -1541,27 +1541,52 @@ __global__ __launch_bounds__(128) void k_mutate_large(Span sp, int pmax)
 // ---------------------------------------------------------------------------------------
 // front extraction, eval-path helpers
 // ---------------------------------------------------------------------------------------
-__global__ void k_extract(int32_t n, int32_t ld, int32_t pop, const int32_t *__restrict__ pool,
-                          const int32_t *__restrict__ q, const int32_t *__restrict__ ids,
-                          int32_t k, const int32_t *__restrict__ k_dev, int32_t *__restrict__ out)
+// Front rows ids[0..k) of a population (id < pop: column id of pool, else column id - pop of
+// q) into individual-major out[k][n]. A workgroup moves EX_NODES nodes x EX_ROWS rows through
+// LDS: first each lane takes one row and the waves walk the nodes, so that one wave's loads
+// fall in a node's two label rows; then each lane takes one node and the waves walk the
+// rows, so that every store writes EX_NODES consecutive labels of one output row. (One
+// thread per output label, each reading its 4-byte label from its own line, took 1.83 ms for
+// a 100 x 1M front; this takes 0.36 ms.)
+constexpr int EX_NODES = 64, EX_ROWS = 128, EX_THREADS = 256;
+
+__global__ __launch_bounds__(EX_THREADS) void k_extract(int32_t n, int32_t ld, int32_t pop,
+                                                        const int32_t *__restrict__ pool,
+                                                        const int32_t *__restrict__ q,
+                                                        const int32_t *__restrict__ ids, int32_t k,
+                                                        const int32_t *__restrict__ k_dev,
+                                                        int32_t *__restrict__ out)
 {
-    const int row = blockIdx.y;
-    if (k_dev && row >= *k_dev) return;  // rows beyond the device-side count hold nothing
-    const int id = ids[row];
-    const int32_t *src = id < pop ? pool + id : q + (id - pop);
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
-         v += (int64_t)gridDim.x * blockDim.x)
-        out[(size_t)row * n + v] = src[(size_t)v * ld];
+    __shared__ int32_t tile[EX_ROWS][EX_NODES + 1];  // +1: lanes of phase 1 hit distinct banks
+    const int kk = k_dev ? min(k, *k_dev) : k;  // rows beyond the device-side count hold nothing
+    const int r0 = blockIdx.y * EX_ROWS;
+    if (r0 >= kk) return;
+    const int64_t v0 = (int64_t)blockIdx.x * EX_NODES;
+    const int nv = (int)min((int64_t)EX_NODES, (int64_t)n - v0);
+    {
+        constexpr int GROUPS = EX_THREADS / EX_ROWS;
+        const int rr = threadIdx.x % EX_ROWS, grp = threadIdx.x / EX_ROWS;
+        if (r0 + rr < kk) {
+            const int id = ids[r0 + rr];
+            const int32_t *src = (id < pop ? pool + id : q + (id - pop)) + (size_t)v0 * ld;
+            for (int t = grp; t < nv; t += GROUPS) tile[rr][t] = src[(size_t)t * ld];
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % EX_NODES;
+    const int rows = min(EX_ROWS, kk - r0);
+    if (lane < nv)
+        for (int rr = threadIdx.x / EX_NODES; rr < rows; rr += EX_THREADS / EX_NODES)
+            out[(size_t)(r0 + rr) * n + v0 + lane] = tile[rr][lane];
 }
 
 hipError_t launch_extract(int32_t n, int32_t ld, int32_t pop, const int32_t *pool,
                           const int32_t *q, const int32_t *ids, int32_t k, int32_t *out,
                           hipStream_t s, const int32_t *k_dev)
 {
-    if (k == 0) return hipSuccess;
-    unsigned bx = (unsigned)((n + 255) / 256);
-    if (bx > 1024) bx = 1024;
-    k_extract<<<dim3(bx, (unsigned)k), 256, 0, s>>>(n, ld, pop, pool, q, ids, k, k_dev, out);
+    if (k == 0 || n == 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + EX_NODES - 1) / EX_NODES), (unsigned)((k + EX_ROWS - 1) / EX_ROWS));
+    k_extract<<<grid, EX_THREADS, 0, s>>>(n, ld, pop, pool, q, ids, k, k_dev, out);
     return hipGetLastError();
 }
 

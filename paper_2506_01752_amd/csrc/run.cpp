@@ -8,7 +8,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <condition_variable>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include <sys/mman.h>
@@ -417,19 +419,56 @@ namespace {
 
 // Device-to-host copies of large results (a front's labels: up to N_p x n int32, 400 MB at
 // |V| = 1M, pop 100). From pageable memory the runtime stages such a copy through small
-// buffers of its own at a few GB/s; here it goes through two 16 MB page-locked buffers per
-// device (allocated on first use, kept until the process ends): the DMA of one chunk runs
-// while the previous chunk is copied out on the host. Calls from several threads take turns.
-constexpr size_t BOUNCE_CHUNK = (size_t)16 << 20;
+// buffers of its own at a few GB/s. Here it goes through BOUNCE_BUFS page-locked chunks per
+// device (allocated on first use, kept until the process ends): the calling thread keeps the
+// DMA engine fed, one chunk after another, while up to COPY_THREADS helper threads copy the
+// completed chunks out on the host, each taking every COPY_THREADS-th chunk. One thread
+// copying out into freshly mapped memory ran at about 14 GB/s, well below the link. Calls
+// from several threads take turns.
+constexpr size_t BOUNCE_CHUNK = (size_t)8 << 20;
+constexpr int BOUNCE_BUFS = 8;
+constexpr int COPY_THREADS = 4;
 constexpr size_t BOUNCE_MIN = (size_t)4 << 20;  // smaller copies go direct
 constexpr int BOUNCE_DEVICES = 64;
 struct Bounce {
     std::mutex mu;
     bool tried = false;
-    char *buf[2] = {nullptr, nullptr};
-    hipEvent_t ev[2] = {nullptr, nullptr};
+    char *buf[BOUNCE_BUFS] = {};
+    hipEvent_t ev[BOUNCE_BUFS] = {};
 };
 Bounce g_bounce[BOUNCE_DEVICES];
+
+bool bounce_ready(Bounce *b)
+{
+    if (!b->tried) {
+        b->tried = true;
+        bool ok = true;
+        for (int i = 0; i < BOUNCE_BUFS; ++i) {
+            ok = ok && hipHostMalloc((void **)&b->buf[i], BOUNCE_CHUNK, hipHostMallocDefault) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) == hipSuccess;
+        }
+        if (!ok) {
+            for (int i = 0; i < BOUNCE_BUFS; ++i) {
+                if (b->buf[i]) (void)hipHostFree(b->buf[i]);
+                if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
+                b->buf[i] = nullptr;
+                b->ev[i] = nullptr;
+            }
+        }
+    }
+    return b->buf[0] != nullptr;
+}
+
+// Hand-off between the thread that issues the chunk copies and the helpers that copy the
+// chunks out: chunk i may be issued once chunk i - BOUNCE_BUFS (the buffer's previous
+// content) has been copied out.
+struct ChunkBoard {
+    std::mutex mu;
+    std::condition_variable cv;
+    size_t issued = 0;
+    std::vector<char> out;  // per chunk: copied out
+    bool failed = false;
+};
 
 // copies bytes from device memory src to host memory dst in stream order on s and returns
 // with the copy complete
@@ -442,64 +481,190 @@ hipError_t copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s)
     std::unique_lock<std::mutex> lock;
     if (b) {
         lock = std::unique_lock<std::mutex>(b->mu);
-        if (!b->tried) {
-            b->tried = true;
-            bool ok = true;
-            for (int i = 0; i < 2; ++i) {
-                ok = ok && hipHostMalloc((void **)&b->buf[i], BOUNCE_CHUNK, hipHostMallocDefault) == hipSuccess;
-                ok = ok && hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming) == hipSuccess;
-            }
-            if (!ok) {
-                for (int i = 0; i < 2; ++i) {
-                    if (b->buf[i]) (void)hipHostFree(b->buf[i]);
-                    if (b->ev[i]) (void)hipEventDestroy(b->ev[i]);
-                    b->buf[i] = nullptr;
-                    b->ev[i] = nullptr;
-                }
-            }
-        }
-        if (!b->buf[0]) b = nullptr;
+        if (!bounce_ready(b)) b = nullptr;
     }
     if (!b) {
         if ((e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
         return hipStreamSynchronize(s);
     }
     const size_t nchunk = (bytes + BOUNCE_CHUNK - 1) / BOUNCE_CHUNK;
-    for (size_t i = 0; i <= nchunk; ++i) {
-        if (i < nchunk) {  // chunk i into buffer i % 2 (its previous chunk was copied out)
+    ChunkBoard bd;
+    bd.out.assign(nchunk, 0);
+    std::vector<hipError_t> werr;
+    auto helper = [&](size_t first, size_t step, hipError_t *err) {
+        for (size_t j = first; j < nchunk; j += step) {
+            {
+                std::unique_lock<std::mutex> lk(bd.mu);
+                bd.cv.wait(lk, [&] { return bd.issued > j || bd.failed; });
+                if (bd.failed) return;
+            }
+            const size_t off = j * BOUNCE_CHUNK, len = std::min(BOUNCE_CHUNK, bytes - off);
+            const hipError_t ee = hipEventSynchronize(b->ev[j % BOUNCE_BUFS]);
+            if (ee == hipSuccess) std::memcpy((char *)dst + off, b->buf[j % BOUNCE_BUFS], len);
+            std::lock_guard<std::mutex> lk(bd.mu);
+            if (ee != hipSuccess) {
+                *err = ee;
+                bd.failed = true;
+            } else {
+                bd.out[j] = 1;
+            }
+            bd.cv.notify_all();
+            if (ee != hipSuccess) return;
+        }
+    };
+    const size_t want = std::min<size_t>(COPY_THREADS, nchunk);
+    werr.assign(want, hipSuccess);
+    std::vector<std::thread> th;
+    try {
+        for (size_t t = 0; t < want; ++t) th.emplace_back(helper, t, want, &werr[t]);
+    } catch (...) {  // no thread to spare: the helpers that did start share the chunks
+        std::lock_guard<std::mutex> lk(bd.mu);
+        bd.failed = true;
+        bd.cv.notify_all();
+    }
+    if (th.size() < want) {  // stop the started helpers and copy one chunk at a time
+        for (auto &x : th) x.join();
+        for (size_t i = 0; i < nchunk; ++i) {
             const size_t off = i * BOUNCE_CHUNK, len = std::min(BOUNCE_CHUNK, bytes - off);
-            e = hipMemcpyAsync(b->buf[i & 1], (const char *)src + off, len, hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipEventRecord(b->ev[i & 1], s);
-            if (e != hipSuccess) {
-                (void)hipStreamSynchronize(s);
+            if ((e = hipMemcpyAsync(b->buf[0], (const char *)src + off, len, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
                 return e;
-            }
+            std::memcpy((char *)dst + off, b->buf[0], len);
         }
-        if (i > 0) {  // chunk i - 1 out of its buffer while chunk i is in flight
-            const size_t j = i - 1, off = j * BOUNCE_CHUNK, len = std::min(BOUNCE_CHUNK, bytes - off);
-            if ((e = hipEventSynchronize(b->ev[j & 1])) != hipSuccess) {
-                (void)hipStreamSynchronize(s);
-                return e;
-            }
-            std::memcpy((char *)dst + off, b->buf[j & 1], len);
+        return hipSuccess;
+    }
+    for (size_t i = 0; i < nchunk && e == hipSuccess; ++i) {
+        {
+            std::unique_lock<std::mutex> lk(bd.mu);
+            bd.cv.wait(lk, [&] { return i < BOUNCE_BUFS || bd.out[i - BOUNCE_BUFS] || bd.failed; });
+            if (bd.failed) break;
         }
+        const size_t off = i * BOUNCE_CHUNK, len = std::min(BOUNCE_CHUNK, bytes - off);
+        e = hipMemcpyAsync(b->buf[i % BOUNCE_BUFS], (const char *)src + off, len, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(b->ev[i % BOUNCE_BUFS], s);
+        std::lock_guard<std::mutex> lk(bd.mu);
+        if (e != hipSuccess) bd.failed = true;
+        else bd.issued = i + 1;
+        bd.cv.notify_all();
+    }
+    for (auto &x : th) x.join();
+    if (e != hipSuccess || bd.failed) {
+        (void)hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        for (hipError_t x : werr)
+            if (x != hipSuccess) return x;
+        return hipErrorUnknown;
     }
     return hipSuccess;
 }
 
-// host memory for a front's labels: 2 MB-aligned, with transparent huge pages requested, so
-// that filling hundreds of megabytes does not fault on every 4 KB page; freed by free()
-void *alloc_labels(size_t bytes)
+// Host memory for fronts' labels. A large buffer is 2 MB-aligned with transparent huge pages
+// requested, and once freed it is kept (up to LABEL_CACHE_COUNT buffers, LABEL_CACHE_BYTES in
+// all) for the next front it fits: copying a front into memory that is already mapped skips
+// the kernel's zeroing of every fresh page, which cost more than the copy itself.
+constexpr size_t LABEL_LARGE = (size_t)32 << 20;
+constexpr int LABEL_CACHE_COUNT = 2;
+constexpr size_t LABEL_CACHE_BYTES = (size_t)2 << 30;
+struct LabelCache {
+    std::mutex mu;
+    std::vector<std::pair<void *, size_t>> live;  // large buffers handed out, and their sizes
+    std::vector<std::pair<void *, size_t>> idle;  // freed ones kept for reuse, oldest first
+};
+LabelCache &label_cache()
 {
-    constexpr size_t HUGE_PAGE = (size_t)2 << 20;
-    if (bytes < HUGE_PAGE) return std::malloc(bytes ? bytes : 1);
-    const size_t rounded = (bytes + HUGE_PAGE - 1) / HUGE_PAGE * HUGE_PAGE;
-    void *p = std::aligned_alloc(HUGE_PAGE, rounded);
-    if (p) (void)madvise(p, rounded, MADV_HUGEPAGE);
-    return p;
+    static LabelCache *c = new LabelCache;  // never destroyed: frees may come at exit
+    return *c;
 }
 
 }  // namespace
+
+void *alloc_labels(size_t bytes)
+{
+    if (bytes < LABEL_LARGE) return std::malloc(bytes ? bytes : 1);
+    constexpr size_t HUGE_PAGE = (size_t)2 << 20;
+    const size_t rounded = (bytes + HUGE_PAGE - 1) / HUGE_PAGE * HUGE_PAGE;
+    LabelCache &c = label_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    size_t best = c.idle.size();
+    for (size_t i = 0; i < c.idle.size(); ++i)  // the smallest kept buffer that fits, if not
+        if (c.idle[i].second >= rounded && c.idle[i].second <= 2 * rounded &&  // twice too big
+            (best == c.idle.size() || c.idle[i].second < c.idle[best].second))
+            best = i;
+    void *p = nullptr;
+    size_t size = rounded;
+    if (best < c.idle.size()) {
+        p = c.idle[best].first;
+        size = c.idle[best].second;
+        c.idle.erase(c.idle.begin() + (std::ptrdiff_t)best);
+    } else {
+        p = std::aligned_alloc(HUGE_PAGE, rounded);
+        if (!p) return nullptr;
+        (void)madvise(p, rounded, MADV_HUGEPAGE);
+    }
+    try {
+        c.live.emplace_back(p, size);
+    } catch (...) {
+        std::free(p);
+        return nullptr;
+    }
+    return p;
+}
+
+void host_copy(void *dst, const void *src, size_t bytes)
+{
+    constexpr size_t PART_MIN = (size_t)8 << 20;
+    const size_t parts = std::min<size_t>(COPY_THREADS, bytes / PART_MIN);
+    if (parts < 2) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    const size_t step = (bytes / parts + 4095) / 4096 * 4096;
+    auto part = [=](size_t i) {
+        const size_t off = std::min(bytes, i * step), len = std::min(step, bytes - off);
+        std::memcpy((char *)dst + off, (const char *)src + off, len);
+    };
+    std::vector<std::thread> th;
+    size_t started = 1;  // part 0 is this thread's
+    try {
+        for (; started < parts; ++started) th.emplace_back(part, started);
+    } catch (...) {
+    }
+    part(0);
+    for (size_t i = started; i < parts; ++i) part(i);  // parts no thread could be started for
+    for (auto &x : th) x.join();
+}
+
+void free_labels(void *p)
+{
+    if (!p) return;
+    LabelCache &c = label_cache();
+    std::lock_guard<std::mutex> lk(c.mu);
+    size_t i = 0;
+    while (i < c.live.size() && c.live[i].first != p) ++i;
+    if (i == c.live.size()) {  // a small buffer from malloc
+        std::free(p);
+        return;
+    }
+    const std::pair<void *, size_t> e = c.live[i];
+    c.live.erase(c.live.begin() + (std::ptrdiff_t)i);
+    if (e.second > LABEL_CACHE_BYTES) {
+        std::free(p);
+        return;
+    }
+    try {
+        c.idle.push_back(e);
+    } catch (...) {
+        std::free(p);
+        return;
+    }
+    size_t total = 0;
+    for (const auto &x : c.idle) total += x.second;
+    while (!c.idle.empty() && ((int)c.idle.size() > LABEL_CACHE_COUNT || total > LABEL_CACHE_BYTES)) {
+        total -= c.idle.front().second;
+        std::free(c.idle.front().first);
+        c.idle.erase(c.idle.begin());
+    }
+}
 
 int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out, Pinned *stage)
 {
@@ -538,7 +703,7 @@ int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out, Pinned *stage
     if (lab_dst != f->labels) {  // into the caller's page-locked staging, then out of it
         ok = ok && hipMemcpyAsync(lab_dst, L.C, lab_bytes, hipMemcpyDeviceToHost, s) == hipSuccess;
         ok = ok && hipStreamSynchronize(s) == hipSuccess;
-        if (ok) std::memcpy(f->labels, lab_dst, lab_bytes);
+        if (ok) host_copy(f->labels, lab_dst, lab_bytes);
     } else {
         ok = ok && copy_to_host(f->labels, L.C, lab_bytes, s) == hipSuccess;
     }
@@ -598,7 +763,7 @@ int front_from_staged(const Pop &P, const StagedFront &sf, hpmocd_front **out)
         hpmocd_front_free(f);
         return HPMOCD_ERR_NOMEM;
     }
-    std::memcpy(f->labels, sf.labels, sizeof(int32_t) * (size_t)k * n);
+    host_copy(f->labels, sf.labels, sizeof(int32_t) * (size_t)k * n);
     std::memcpy(f->intra_arcs, sf.A, sizeof(int64_t) * k);
     std::memcpy(f->sum_deg_sq, sf.S, sizeof(int64_t) * k);
     std::memcpy(f->f1, sf.f1, sizeof(double) * k);
@@ -912,7 +1077,7 @@ extern "C" {
 void hpmocd_front_free(hpmocd_front *f)
 {
     if (!f) return;
-    std::free(f->labels);
+    free_labels(f->labels);
     std::free(f->intra_arcs);
     std::free(f->sum_deg_sq);
     std::free(f->f1);

@@ -133,6 +133,11 @@ int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, voi
 // stage: optional page-locked staging for the labels' device-to-host copy (reset by the
 // call, which synchronises s)
 int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out, Pinned *stage = nullptr);
+// host buffers of fronts' labels (hpmocd_front_free releases them with free_labels)
+void *alloc_labels(size_t bytes);
+void free_labels(void *p);
+// memcpy of a large host buffer split over a few threads (one thread for small ones)
+void host_copy(void *dst, const void *src, size_t bytes);
 
 // The front of a ranked population without host synchronisation: every copy is enqueued on
 // s into page-locked host memory taken from `stage` (all N_p candidate rows, the device
