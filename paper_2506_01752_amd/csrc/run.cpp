@@ -418,17 +418,17 @@ int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, voi
 namespace {
 
 // Device-to-host copies of large results (a front's labels: up to N_p x n int32, 400 MB at
-// |V| = 1M, pop 100). From pageable memory the runtime stages such a copy through small
-// buffers of its own at a few GB/s. Here it goes through BOUNCE_BUFS page-locked chunks per
-// device (allocated on first use, kept until the process ends): the calling thread keeps the
-// DMA engine fed, one chunk after another, while up to COPY_THREADS helper threads copy the
-// completed chunks out on the host, each taking every COPY_THREADS-th chunk. One thread
-// copying out into freshly mapped memory ran at about 14 GB/s, well below the link. Calls
-// from several threads take turns.
+// |V| = 1M, pop 100; a batch's fronts together). From pageable memory the runtime stages such
+// a copy through small buffers of its own at a few GB/s. Here the pieces to copy are packed
+// into BOUNCE_BUFS page-locked chunks per device (allocated on first use, kept until the
+// process ends): the calling thread keeps the DMA engine fed, one chunk after another, while
+// up to COPY_THREADS helper threads copy completed chunks out on the host, each taking every
+// COPY_THREADS-th chunk. One thread copying out into freshly mapped memory ran at about 14
+// GB/s, well below the link. Calls from several threads take turns.
 constexpr size_t BOUNCE_CHUNK = (size_t)8 << 20;
 constexpr int BOUNCE_BUFS = 8;
 constexpr int COPY_THREADS = 4;
-constexpr size_t BOUNCE_MIN = (size_t)4 << 20;  // smaller copies go direct
+constexpr size_t BOUNCE_MIN = (size_t)4 << 20;  // less in all goes direct
 constexpr int BOUNCE_DEVICES = 64;
 struct Bounce {
     std::mutex mu;
@@ -470,24 +470,56 @@ struct ChunkBoard {
     bool failed = false;
 };
 
-// copies bytes from device memory src to host memory dst in stream order on s and returns
-// with the copy complete
-hipError_t copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s)
+// one piece of a chunk: bytes [off, off + len) of the chunk go to dst, from src on the device
+struct Piece {
+    char *dst;
+    const char *src;
+    size_t len, off;
+};
+
+}  // namespace
+
+// Copies every segment from device memory to host memory in stream order on s; returns with
+// the copies complete.
+hipError_t copy_segments(const HostSeg *segs, size_t count, hipStream_t s)
 {
+    size_t total = 0;
+    for (size_t i = 0; i < count; ++i) total += segs[i].bytes;
     int dev = -1;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
-    Bounce *b = (dev >= 0 && dev < BOUNCE_DEVICES && bytes >= BOUNCE_MIN) ? &g_bounce[dev] : nullptr;
+    Bounce *b = (dev >= 0 && dev < BOUNCE_DEVICES && total >= BOUNCE_MIN) ? &g_bounce[dev] : nullptr;
     std::unique_lock<std::mutex> lock;
     if (b) {
         lock = std::unique_lock<std::mutex>(b->mu);
         if (!bounce_ready(b)) b = nullptr;
     }
     if (!b) {
-        if ((e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+        for (size_t i = 0; i < count; ++i)
+            if (segs[i].bytes &&
+                (e = hipMemcpyAsync(segs[i].dst, segs[i].src, segs[i].bytes, hipMemcpyDeviceToHost, s)) != hipSuccess) {
+                (void)hipStreamSynchronize(s);
+                return e;
+            }
         return hipStreamSynchronize(s);
     }
-    const size_t nchunk = (bytes + BOUNCE_CHUNK - 1) / BOUNCE_CHUNK;
+    // pack the segments into chunks, each piece 256-byte aligned in its chunk
+    std::vector<std::vector<Piece>> chunks(1);
+    size_t fill = 0;
+    for (size_t i = 0; i < count; ++i) {
+        for (size_t done = 0; done < segs[i].bytes;) {
+            fill = (fill + 255) / 256 * 256;
+            if (fill >= BOUNCE_CHUNK) {
+                chunks.emplace_back();
+                fill = 0;
+            }
+            const size_t len = std::min(segs[i].bytes - done, BOUNCE_CHUNK - fill);
+            chunks.back().push_back({(char *)segs[i].dst + done, (const char *)segs[i].src + done, len, fill});
+            fill += len;
+            done += len;
+        }
+    }
+    const size_t nchunk = chunks.size();
     ChunkBoard bd;
     bd.out.assign(nchunk, 0);
     std::vector<hipError_t> werr;
@@ -498,9 +530,9 @@ hipError_t copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s)
                 bd.cv.wait(lk, [&] { return bd.issued > j || bd.failed; });
                 if (bd.failed) return;
             }
-            const size_t off = j * BOUNCE_CHUNK, len = std::min(BOUNCE_CHUNK, bytes - off);
             const hipError_t ee = hipEventSynchronize(b->ev[j % BOUNCE_BUFS]);
-            if (ee == hipSuccess) std::memcpy((char *)dst + off, b->buf[j % BOUNCE_BUFS], len);
+            if (ee == hipSuccess)
+                for (const Piece &pc : chunks[j]) std::memcpy(pc.dst, b->buf[j % BOUNCE_BUFS] + pc.off, pc.len);
             std::lock_guard<std::mutex> lk(bd.mu);
             if (ee != hipSuccess) {
                 *err = ee;
@@ -512,24 +544,30 @@ hipError_t copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s)
             if (ee != hipSuccess) return;
         }
     };
+    auto issue = [&](size_t i, char *buf) {
+        hipError_t ee = hipSuccess;
+        for (const Piece &pc : chunks[i])
+            if ((ee = hipMemcpyAsync(buf + pc.off, pc.src, pc.len, hipMemcpyDeviceToHost, s)) != hipSuccess) break;
+        return ee;
+    };
     const size_t want = std::min<size_t>(COPY_THREADS, nchunk);
     werr.assign(want, hipSuccess);
     std::vector<std::thread> th;
     try {
         for (size_t t = 0; t < want; ++t) th.emplace_back(helper, t, want, &werr[t]);
-    } catch (...) {  // no thread to spare: the helpers that did start share the chunks
+    } catch (...) {  // no thread to spare: stop the helpers that did start
         std::lock_guard<std::mutex> lk(bd.mu);
         bd.failed = true;
         bd.cv.notify_all();
     }
-    if (th.size() < want) {  // stop the started helpers and copy one chunk at a time
+    if (th.size() < want) {  // and copy one chunk at a time
         for (auto &x : th) x.join();
         for (size_t i = 0; i < nchunk; ++i) {
-            const size_t off = i * BOUNCE_CHUNK, len = std::min(BOUNCE_CHUNK, bytes - off);
-            if ((e = hipMemcpyAsync(b->buf[0], (const char *)src + off, len, hipMemcpyDeviceToHost, s)) != hipSuccess ||
-                (e = hipStreamSynchronize(s)) != hipSuccess)
+            if ((e = issue(i, b->buf[0])) != hipSuccess || (e = hipStreamSynchronize(s)) != hipSuccess) {
+                (void)hipStreamSynchronize(s);
                 return e;
-            std::memcpy((char *)dst + off, b->buf[0], len);
+            }
+            for (const Piece &pc : chunks[i]) std::memcpy(pc.dst, b->buf[0] + pc.off, pc.len);
         }
         return hipSuccess;
     }
@@ -539,8 +577,7 @@ hipError_t copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s)
             bd.cv.wait(lk, [&] { return i < BOUNCE_BUFS || bd.out[i - BOUNCE_BUFS] || bd.failed; });
             if (bd.failed) break;
         }
-        const size_t off = i * BOUNCE_CHUNK, len = std::min(BOUNCE_CHUNK, bytes - off);
-        e = hipMemcpyAsync(b->buf[i % BOUNCE_BUFS], (const char *)src + off, len, hipMemcpyDeviceToHost, s);
+        e = issue(i, b->buf[i % BOUNCE_BUFS]);
         if (e == hipSuccess) e = hipEventRecord(b->ev[i % BOUNCE_BUFS], s);
         std::lock_guard<std::mutex> lk(bd.mu);
         if (e != hipSuccess) bd.failed = true;
@@ -557,6 +594,14 @@ hipError_t copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s)
     }
     return hipSuccess;
 }
+
+hipError_t copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    const HostSeg seg{dst, src, bytes};
+    return copy_segments(&seg, 1, s);
+}
+
+namespace {
 
 // Host memory for fronts' labels. A large buffer is 2 MB-aligned with transparent huge pages
 // requested, and once freed it is kept (up to LABEL_CACHE_COUNT buffers, LABEL_CACHE_BYTES in
@@ -668,6 +713,10 @@ void free_labels(void *p)
 
 int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out, Pinned *stage)
 {
+    if (!stage) {
+        const Pop *pp = &P;
+        return extract_fronts(&pp, 1, s, out);
+    }
     const RunLayout &L = P.L;
     const int32_t n = P.G->n, pop = P.c.pop;
     int32_t ks[2] = {0, 0};  // front size and Alg. 3's choice (both computed by k_final)
@@ -714,6 +763,89 @@ int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out, Pinned *stage
     }
     f->selected = ks[1];
     *out = f;
+    return HPMOCD_OK;
+}
+
+int extract_fronts(const Pop *const *pops, int32_t count, hipStream_t s, hpmocd_front **outs)
+{
+    for (int32_t i = 0; i < count; ++i) outs[i] = nullptr;
+    if (count <= 0) return HPMOCD_OK;
+    // every population's front size and Alg. 3's choice (k_final), in one round trip; for
+    // many populations into page-locked memory, since a copy into pageable memory returns
+    // only once it is done
+    int32_t *ks = nullptr;
+    std::vector<int32_t> ks_pageable;
+    if (count < 8 ||
+        hipHostMalloc((void **)&ks, sizeof(int32_t) * 2 * (size_t)count, hipHostMallocDefault) != hipSuccess) {
+        ks = nullptr;
+        try {
+            ks_pageable.assign(2 * (size_t)count, 0);
+        } catch (...) {
+            return HPMOCD_ERR_NOMEM;
+        }
+    }
+    struct HostFree {
+        int32_t *p;
+        ~HostFree()
+        {
+            if (p) (void)hipHostFree(p);
+        }
+    } ks_guard{ks};
+    int32_t *kv = ks ? ks : ks_pageable.data();
+    for (int32_t i = 0; i < count; ++i) {
+        const RunLayout &L = pops[i]->L;
+        HIP_TRY(hipMemcpyAsync(&kv[2 * i], L.st.fr_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(&kv[2 * i + 1], L.st.fr_sel, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int32_t i = 0; i < count; ++i) {
+        const int32_t k = kv[2 * i], sel = kv[2 * i + 1];
+        if (k < 1 || k > pops[i]->c.pop || sel < 0 || sel >= k) return HPMOCD_ERR_HIP;
+    }
+    // each front's rows into its population's C plane (free after the last generation)
+    for (int32_t i = 0; i < count; ++i) {
+        const Pop &P = *pops[i];
+        const RunLayout &L = P.L;
+        HIP_TRY(launch_extract(P.G->n, P.c.ld, P.c.pop, L.pool[P.cur], L.q[P.cur], L.st.fr_id,
+                               kv[2 * i], L.C, s));
+    }
+    auto fail = [&](int rc) {
+        for (int32_t i = 0; i < count; ++i) {
+            hpmocd_front_free(outs[i]);
+            outs[i] = nullptr;
+        }
+        return rc;
+    };
+    std::vector<HostSeg> segs;
+    try {
+        segs.reserve(5 * (size_t)count);
+    } catch (...) {
+        return HPMOCD_ERR_NOMEM;
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        const Pop &P = *pops[i];
+        const RunLayout &L = P.L;
+        const int32_t k = kv[2 * i], n = P.G->n;
+        hpmocd_front *f = (hpmocd_front *)std::calloc(1, sizeof(hpmocd_front));
+        if (!f) return fail(HPMOCD_ERR_NOMEM);
+        outs[i] = f;
+        f->n_solutions = k;
+        f->n_nodes = n;
+        f->selected = kv[2 * i + 1];
+        const size_t lab_bytes = sizeof(int32_t) * (size_t)k * n;
+        f->labels = (int32_t *)alloc_labels(lab_bytes);
+        f->intra_arcs = (int64_t *)std::malloc(sizeof(int64_t) * k);
+        f->sum_deg_sq = (int64_t *)std::malloc(sizeof(int64_t) * k);
+        f->f1 = (double *)std::malloc(sizeof(double) * k);
+        f->f2 = (double *)std::malloc(sizeof(double) * k);
+        if (!f->labels || !f->intra_arcs || !f->sum_deg_sq || !f->f1 || !f->f2) return fail(HPMOCD_ERR_NOMEM);
+        segs.push_back({f->labels, L.C, lab_bytes});
+        segs.push_back({f->intra_arcs, L.st.fr_A, sizeof(int64_t) * k});
+        segs.push_back({f->sum_deg_sq, L.st.fr_S, sizeof(int64_t) * k});
+        segs.push_back({f->f1, L.st.fr_f1, sizeof(double) * k});
+        segs.push_back({f->f2, L.st.fr_f2, sizeof(double) * k});
+    }
+    if (copy_segments(segs.data(), segs.size(), s) != hipSuccess) return fail(HPMOCD_ERR_HIP);
     return HPMOCD_OK;
 }
 
@@ -1014,15 +1146,14 @@ int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_par
 
     // phase 4: first front of every population
     HIP_TRY(B.meta[1].one(ONE_FINAL, s));
-    for (int32_t i = 0; i < count; ++i) outs[i] = nullptr;
-    for (int32_t i = 0; i < count; ++i) {
-        if ((rc = extract_front(B.pops[i], s, &outs[i]))) {
-            for (int32_t j = 0; j < i; ++j) {
-                hpmocd_front_free(outs[j]);
-                outs[j] = nullptr;
-            }
-            return rc;
+    {
+        std::vector<const Pop *> pp;
+        try {
+            for (const Pop &P : B.pops) pp.push_back(&P);
+        } catch (...) {
+            return HPMOCD_ERR_NOMEM;
         }
+        if ((rc = extract_fronts(pp.data(), count, s, outs))) return rc;
     }
     if (prof) {
         HIP_TRY(hipEventRecord(e_end, s));

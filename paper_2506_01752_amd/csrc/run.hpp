@@ -133,6 +133,17 @@ int emit_state(const Pop &P, int32_t gen, hipStream_t s, hpmocd_trace_fn fn, voi
 // stage: optional page-locked staging for the labels' device-to-host copy (reset by the
 // call, which synchronises s)
 int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out, Pinned *stage = nullptr);
+// Fronts of several populations after their final ranking (k_final has run), one stream
+// drain for all of them; on error no front is returned.
+int extract_fronts(const Pop *const *pops, int32_t count, hipStream_t s, hpmocd_front **outs);
+// device-to-host copies: bytes from src (device) to dst (host); returns with all complete
+struct HostSeg {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+hipError_t copy_segments(const HostSeg *segs, size_t count, hipStream_t s);
+hipError_t copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s);
 // host buffers of fronts' labels (hpmocd_front_free releases them with free_labels)
 void *alloc_labels(size_t bytes);
 void free_labels(void *p);
