@@ -9,6 +9,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <condition_variable>
+#include <initializer_list>
 #include <mutex>
 #include <thread>
 #include <vector>
@@ -601,6 +602,17 @@ hipError_t copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s)
     return copy_segments(&seg, 1, s);
 }
 
+// Small device-to-host copies issued together; drains s whatever happens, so that no copy
+// outlives host buffers of the caller's frame on an error return.
+hipError_t copy_small(std::initializer_list<HostSeg> segs, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    for (const HostSeg &g : segs)
+        if (e == hipSuccess && g.bytes) e = hipMemcpyAsync(g.dst, g.src, g.bytes, hipMemcpyDeviceToHost, s);
+    const hipError_t es = hipStreamSynchronize(s);
+    return e != hipSuccess ? e : es;
+}
+
 namespace {
 
 // Host memory for fronts' labels. A large buffer is 2 MB-aligned with transparent huge pages
@@ -720,9 +732,9 @@ int extract_front(const Pop &P, hipStream_t s, hpmocd_front **out, Pinned *stage
     const RunLayout &L = P.L;
     const int32_t n = P.G->n, pop = P.c.pop;
     int32_t ks[2] = {0, 0};  // front size and Alg. 3's choice (both computed by k_final)
-    HIP_TRY(hipMemcpyAsync(&ks[0], L.st.fr_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(&ks[1], L.st.fr_sel, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    hipError_t e = hipMemcpyAsync(&ks[0], L.st.fr_count, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&ks[1], L.st.fr_sel, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (hipStreamSynchronize(s) != hipSuccess || e != hipSuccess) return HPMOCD_ERR_HIP;  // ks in scope
     const int32_t k = ks[0];
     if (k < 1 || k > pop || ks[1] < 0 || ks[1] >= k) return HPMOCD_ERR_HIP;
     HIP_TRY(launch_extract(n, P.c.ld, pop, L.pool[P.cur], L.q[P.cur], L.st.fr_id, k, L.C, s));
@@ -784,15 +796,17 @@ int extract_fronts(const Pop *const *pops, int32_t count, hipStream_t s, hpmocd_
             return HPMOCD_ERR_NOMEM;
         }
     }
-    struct HostFree {
+    struct HostFree {  // drains s first: no copy into ks is left in flight, whatever return
         int32_t *p;
+        hipStream_t s;
         ~HostFree()
         {
+            (void)hipStreamSynchronize(s);
             if (p) (void)hipHostFree(p);
         }
-    } ks_guard{ks};
+    } ks_guard{ks, s};
     int32_t *kv = ks ? ks : ks_pageable.data();
-    for (int32_t i = 0; i < count; ++i) {
+    for (int32_t i = 0; i < count; ++i) {  // ks_guard drains s on an early return
         const RunLayout &L = pops[i]->L;
         HIP_TRY(hipMemcpyAsync(&kv[2 * i], L.st.fr_count, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipMemcpyAsync(&kv[2 * i + 1], L.st.fr_sel, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1382,9 +1396,8 @@ int hpmocd_resume(const hpmocd_graph *G, const hpmocd_params *p, const hpmocd_sn
         HIP_TRY(mv.one(ONE_ZERO_ACC, s));
         HIP_TRY(launch_fitness_kinds(mv, s, nullptr));
         std::vector<int64_t> A(pop), S(pop);
-        HIP_TRY(hipMemcpyAsync(A.data(), ev.fit_A, sizeof(int64_t) * pop, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(S.data(), ev.fit_S, sizeof(int64_t) * pop, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
+        HIP_TRY(copy_small({{A.data(), ev.fit_A, sizeof(int64_t) * pop},
+                            {S.data(), ev.fit_S, sizeof(int64_t) * pop}}, s));
         for (int32_t i = 0; i < pop; ++i)
             if (A[i] != sn->A[i] || S[i] != sn->S[i]) return HPMOCD_ERR_ARG;
     }
@@ -1468,11 +1481,8 @@ int eval_on(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, void 
     HIP_TRY(hipMemcpyAsync(&bad, d_bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (bad) return HPMOCD_ERR_RANGE;  // evaluated with those labels replaced by 0
-    HIP_TRY(hipMemcpyAsync(A, dA, sizeof(int64_t) * n_ind, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(S, dS, sizeof(int64_t) * n_ind, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(f1, df1, sizeof(double) * n_ind, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(f2, df2, sizeof(double) * n_ind, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(copy_small({{A, dA, sizeof(int64_t) * n_ind}, {S, dS, sizeof(int64_t) * n_ind},
+                        {f1, df1, sizeof(double) * n_ind}, {f2, df2, sizeof(double) * n_ind}}, s));
     if (kernel_ms) *kernel_ms = elapsed(a, b);
     return HPMOCD_OK;
 }

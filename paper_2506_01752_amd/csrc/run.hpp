@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <initializer_list>
 #include <vector>
 
 #include "host.hpp"
@@ -144,6 +145,8 @@ struct HostSeg {
 };
 hipError_t copy_segments(const HostSeg *segs, size_t count, hipStream_t s);
 hipError_t copy_to_host(void *dst, const void *src, size_t bytes, hipStream_t s);
+// small copies issued together; drains s whatever happens (also on an error)
+hipError_t copy_small(std::initializer_list<HostSeg> segs, hipStream_t s);
 // host buffers of fronts' labels (hpmocd_front_free releases them with free_labels)
 void *alloc_labels(size_t bytes);
 void free_labels(void *p);

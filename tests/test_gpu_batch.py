@@ -123,3 +123,25 @@ def test_batch_largest_benchmark_graphs_full_run_against_oracle(hp):
                          mutation_p=0.1, parents_per_child=4, seed=0, threads=threads)
         print(f"  graph {i} (n={g.n}, m={g.m}): front {len(ref.A)}", flush=True)
         assert same(fronts[pick.index(i)], ref), f"benchmark graph {i} differs from the oracle"
+
+
+def test_batch_many_fronts_through_one_pipelined_copy(hp):
+    """Thirty-two fronts of |V| = 40,000 at pop 16 (up to 2.5 MB of labels each, tens of MB
+    together): the batch copies them to the host in one pipelined pass, the pieces of many
+    fronts (and their small objective arrays) sharing page-locked chunks and crossing chunk
+    boundaries; each single run copies its front on its own. Every front must agree."""
+    import torch
+    s = torch.cuda.Stream()
+    graphs = [synth.batch_graph(dict(p, n=40000, mean_deg=8.0))
+              for p in synth.batch_params(32, seed=7)]
+    dgs = [hp.Graph(g.row_ptr, g.col) for g in graphs]
+    p = hp.make_params(pop_size=16, generations=3, seed=11)
+    fronts = hp.run_batch(dgs, p, stream=s)
+    total = sum(f.labels.nbytes for f in fronts)
+    print(f"{len(fronts)} fronts, {total / 2**20:.1f} MiB of labels", flush=True)
+    assert total > (8 << 20)  # more than one page-locked chunk
+    for i, dg in enumerate(dgs):
+        assert same(fronts[i], hp.run(dg, p, stream=s)), f"front {i} differs from its single run"
+    g = graphs[5]
+    ref = oracle.run(g.row_ptr, g.col, pop_size=16, generations=3, seed=11, threads=4)
+    assert same(fronts[5], ref)
