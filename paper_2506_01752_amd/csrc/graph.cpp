@@ -273,18 +273,20 @@ const char *hpmocd_strerror(int status)
 int hpmocd_graph_create(int32_t n, const int32_t *row_ptr, const int32_t *col,
                         hpmocd_graph **out)
 {
-    if (!out) return HPMOCD_ERR_ARG;
-    HostGraph h;
-    int rc = prepare_graph(n, row_ptr, col, &h);
-    if (rc) return rc;
-    hpmocd_graph *g = new (std::nothrow) hpmocd_graph;
-    if (!g) return HPMOCD_ERR_NOMEM;
-    if ((rc = place_graph(h, nullptr, nullptr, g))) {
-        hpmocd_graph_destroy(g);
-        return rc;
-    }
-    *out = g;
-    return HPMOCD_OK;
+    return c_guard([&]() -> int {
+        if (!out) return HPMOCD_ERR_ARG;
+        HostGraph h;
+        int rc = prepare_graph(n, row_ptr, col, &h);
+        if (rc) return rc;
+        hpmocd_graph *g = new (std::nothrow) hpmocd_graph;
+        if (!g) return HPMOCD_ERR_NOMEM;
+        if ((rc = place_graph(h, nullptr, nullptr, g))) {
+            hpmocd_graph_destroy(g);
+            return rc;
+        }
+        *out = g;
+        return HPMOCD_OK;
+    });
 }
 
 void hpmocd_graph_destroy(hpmocd_graph *g)

@@ -29,6 +29,19 @@ namespace hpm {
         if (e_ != hipSuccess) return HPMOCD_ERR_HIP;    \
     } while (0)
 
+// Runs an entry point's body: no exception leaves the C ABI. The library throws only when
+// host resources run out (an allocation, a thread), which is reported as HPMOCD_ERR_NOMEM;
+// stream-draining guards inside the body run while the exception unwinds.
+template <class F>
+int c_guard(F &&f) noexcept
+{
+    try {
+        return f();
+    } catch (...) {
+        return HPMOCD_ERR_NOMEM;
+    }
+}
+
 // Waits for stream s when it leaves scope: an entry point that returns early on an error
 // leaves no kernel running on memory its caller may free next (on success s is already
 // drained, so the wait costs nothing).

@@ -44,13 +44,15 @@ extern "C" int hpmocd_eval_noalloc(const hpmocd_graph *G, const int32_t *d_label
                                    int32_t n_ind, void *stream, int64_t *A, int64_t *S,
                                    double *f1, double *f2)
 {
-    if (!G || !d_labels || n_ind < 1 || !A || !S || !f1 || !f2) return HPMOCD_ERR_ARG;
-    int rc = check_device(G);
-    if (rc) return rc;
-    size_t need = 0;
-    if ((rc = hpmocd_eval_workspace_size(G, n_ind, &need))) return rc;
-    if (need > HPMOCD_NOALLOC_SCRATCH_BYTES) return HPMOCD_ERR_SCRATCH;
-    void *ws = nullptr;
-    if ((rc = scratch_on(G->device, &ws))) return rc;
-    return eval_on(G, d_labels, n_ind, ws, (hipStream_t)stream, A, S, f1, f2, nullptr);
+    return c_guard([&]() -> int {
+        if (!G || !d_labels || n_ind < 1 || !A || !S || !f1 || !f2) return HPMOCD_ERR_ARG;
+        int rc = check_device(G);
+        if (rc) return rc;
+        size_t need = 0;
+        if ((rc = hpmocd_eval_workspace_size(G, n_ind, &need))) return rc;
+        if (need > HPMOCD_NOALLOC_SCRATCH_BYTES) return HPMOCD_ERR_SCRATCH;
+        void *ws = nullptr;
+        if ((rc = scratch_on(G->device, &ws))) return rc;
+        return eval_on(G, d_labels, n_ind, ws, (hipStream_t)stream, A, S, f1, f2, nullptr);
+    });
 }

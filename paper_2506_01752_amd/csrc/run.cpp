@@ -1264,55 +1264,67 @@ void hpmocd_front_free(hpmocd_front *f)
 
 int hpmocd_workspace_size(const hpmocd_graph *g, const hpmocd_params *p, size_t *bytes)
 {
-    if (!g || !bytes) return HPMOCD_ERR_ARG;
-    int rc = check_params(p);
-    if (rc) return rc;
-    *bytes = batch_workspace(&g, 1, p, false);
-    return HPMOCD_OK;
+    return c_guard([&]() -> int {
+        if (!g || !bytes) return HPMOCD_ERR_ARG;
+        int rc = check_params(p);
+        if (rc) return rc;
+        *bytes = batch_workspace(&g, 1, p, false);
+        return HPMOCD_OK;
+    });
 }
 
 int hpmocd_run_ex(const hpmocd_graph *G, const hpmocd_params *p, void *ws, size_t ws_bytes,
                   void *stream, int flags, hpmocd_profile *prof, hpmocd_trace_fn trace,
                   void *user, hpmocd_front **out)
 {
-    if (!G || !out || !p) return HPMOCD_ERR_ARG;
-    if (flags & HPMOCD_AUTOTUNE) return HPMOCD_ERR_ARG;  // batches only
-    hpmocd_front *f = nullptr;
-    int rc = run_batch(&G, 1, p, ws, ws_bytes, stream, flags, prof, trace, user, &f);
-    if (rc == HPMOCD_OK) *out = f;
-    return rc;
+    return c_guard([&]() -> int {
+        if (!G || !out || !p) return HPMOCD_ERR_ARG;
+        if (flags & HPMOCD_AUTOTUNE) return HPMOCD_ERR_ARG;  // batches only
+        hpmocd_front *f = nullptr;
+        int rc = run_batch(&G, 1, p, ws, ws_bytes, stream, flags, prof, trace, user, &f);
+        if (rc == HPMOCD_OK) *out = f;
+        return rc;
+    });
 }
 
 int hpmocd_run(const hpmocd_graph *g, const hpmocd_params *p, void *ws, size_t ws_bytes,
                void *stream, hpmocd_front **out)
 {
-    return hpmocd_run_ex(g, p, ws, ws_bytes, stream, 0, nullptr, nullptr, nullptr, out);
+    return c_guard([&]() -> int {
+        return hpmocd_run_ex(g, p, ws, ws_bytes, stream, 0, nullptr, nullptr, nullptr, out);
+    });
 }
 
 int hpmocd_run_traced(const hpmocd_graph *g, const hpmocd_params *p, void *ws, size_t ws_bytes,
                       void *stream, hpmocd_trace_fn on_generation, void *user,
                       hpmocd_front **out)
 {
-    if (!on_generation) return HPMOCD_ERR_ARG;
-    return hpmocd_run_ex(g, p, ws, ws_bytes, stream, 0, nullptr, on_generation, user, out);
+    return c_guard([&]() -> int {
+        if (!on_generation) return HPMOCD_ERR_ARG;
+        return hpmocd_run_ex(g, p, ws, ws_bytes, stream, 0, nullptr, on_generation, user, out);
+    });
 }
 
 int hpmocd_batch_workspace_size(const hpmocd_graph *const *graphs, int32_t count,
                                 const hpmocd_params *params, int flags, size_t *bytes)
 {
-    if (!bytes) return HPMOCD_ERR_ARG;
-    int rc = check_batch(graphs, count, params);
-    if (rc) return rc;
-    *bytes = batch_workspace(graphs, count, params, (flags & HPMOCD_AUTOTUNE) != 0);
-    return HPMOCD_OK;
+    return c_guard([&]() -> int {
+        if (!bytes) return HPMOCD_ERR_ARG;
+        int rc = check_batch(graphs, count, params);
+        if (rc) return rc;
+        *bytes = batch_workspace(graphs, count, params, (flags & HPMOCD_AUTOTUNE) != 0);
+        return HPMOCD_OK;
+    });
 }
 
 int hpmocd_run_batch(const hpmocd_graph *const *graphs, int32_t count,
                      const hpmocd_params *params, void *ws, size_t ws_bytes, void *stream,
                      int flags, hpmocd_profile *profile, hpmocd_front **outs)
 {
-    return run_batch(graphs, count, params, ws, ws_bytes, stream, flags, profile, nullptr,
-                     nullptr, outs);
+    return c_guard([&]() -> int {
+        return run_batch(graphs, count, params, ws, ws_bytes, stream, flags, profile, nullptr,
+                         nullptr, outs);
+    });
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1330,115 +1342,119 @@ void hpmocd_snapshot_free(hpmocd_snapshot *sn)
 int hpmocd_run_to(const hpmocd_graph *G, const hpmocd_params *p, int32_t stop_gen, void *ws,
                   size_t ws_bytes, void *stream, hpmocd_snapshot **out)
 {
-    if (!G || !p || !out || !ws) return HPMOCD_ERR_ARG;
-    int rc = check_params(p);
-    if (rc) return rc;
-    if (stop_gen < 0 || stop_gen > p->generations) return HPMOCD_ERR_ARG;
-    if ((rc = check_device(G))) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    DrainOnExit drain{s};
-    Batch B;
-    if ((rc = B.setup(&G, 1, p, ws, ws_bytes, Tuning{}, false, s))) return rc;
-    HIP_TRY(launch_init_seq(B.meta[0], s, &B.fork));
-    if ((rc = B.generations(1, stop_gen, s, s != nullptr, nullptr, nullptr, nullptr, false)))
-        return rc;
-    // members in selection order, gathered into row-major rows (C is free here)
-    const Pop &P = B.pops[0];
-    const int32_t n = G->n, pop = p->pop_size;
-    HIP_TRY(launch_extract(n, P.c.ld, pop, P.L.pool[P.cur], P.L.q[P.cur], P.L.st.ps_id, pop,
-                           P.L.C, s));
-    hpmocd_snapshot *sn = (hpmocd_snapshot *)std::calloc(1, sizeof(hpmocd_snapshot));
-    if (!sn) return HPMOCD_ERR_NOMEM;
-    sn->g = stop_gen;
-    sn->pop_size = pop;
-    sn->n_nodes = n;
-    sn->params = *p;
-    sn->graph_hash = G->hash;
-    sn->labels = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)pop * n);
-    sn->A = (int64_t *)std::malloc(sizeof(int64_t) * pop);
-    sn->S = (int64_t *)std::malloc(sizeof(int64_t) * pop);
-    if (!sn->labels || !sn->A || !sn->S) {
-        hpmocd_snapshot_free(sn);
-        return HPMOCD_ERR_NOMEM;
-    }
-    const hipMemcpyKind d2h = hipMemcpyDeviceToHost;
-    bool ok = copy_to_host(sn->labels, P.L.C, sizeof(int32_t) * (size_t)pop * n, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(sn->A, P.L.st.ps_A, sizeof(int64_t) * pop, d2h, s) == hipSuccess;
-    ok = ok && hipMemcpyAsync(sn->S, P.L.st.ps_S, sizeof(int64_t) * pop, d2h, s) == hipSuccess;
-    ok = ok && hipStreamSynchronize(s) == hipSuccess;
-    if (!ok) {
-        hpmocd_snapshot_free(sn);
-        return HPMOCD_ERR_HIP;
-    }
-    *out = sn;
-    return HPMOCD_OK;
+    return c_guard([&]() -> int {
+        if (!G || !p || !out || !ws) return HPMOCD_ERR_ARG;
+        int rc = check_params(p);
+        if (rc) return rc;
+        if (stop_gen < 0 || stop_gen > p->generations) return HPMOCD_ERR_ARG;
+        if ((rc = check_device(G))) return rc;
+        hipStream_t s = (hipStream_t)stream;
+        DrainOnExit drain{s};
+        Batch B;
+        if ((rc = B.setup(&G, 1, p, ws, ws_bytes, Tuning{}, false, s))) return rc;
+        HIP_TRY(launch_init_seq(B.meta[0], s, &B.fork));
+        if ((rc = B.generations(1, stop_gen, s, s != nullptr, nullptr, nullptr, nullptr, false)))
+            return rc;
+        // members in selection order, gathered into row-major rows (C is free here)
+        const Pop &P = B.pops[0];
+        const int32_t n = G->n, pop = p->pop_size;
+        HIP_TRY(launch_extract(n, P.c.ld, pop, P.L.pool[P.cur], P.L.q[P.cur], P.L.st.ps_id, pop,
+                               P.L.C, s));
+        hpmocd_snapshot *sn = (hpmocd_snapshot *)std::calloc(1, sizeof(hpmocd_snapshot));
+        if (!sn) return HPMOCD_ERR_NOMEM;
+        sn->g = stop_gen;
+        sn->pop_size = pop;
+        sn->n_nodes = n;
+        sn->params = *p;
+        sn->graph_hash = G->hash;
+        sn->labels = (int32_t *)std::malloc(sizeof(int32_t) * (size_t)pop * n);
+        sn->A = (int64_t *)std::malloc(sizeof(int64_t) * pop);
+        sn->S = (int64_t *)std::malloc(sizeof(int64_t) * pop);
+        if (!sn->labels || !sn->A || !sn->S) {
+            hpmocd_snapshot_free(sn);
+            return HPMOCD_ERR_NOMEM;
+        }
+        const hipMemcpyKind d2h = hipMemcpyDeviceToHost;
+        bool ok = copy_to_host(sn->labels, P.L.C, sizeof(int32_t) * (size_t)pop * n, s) == hipSuccess;
+        ok = ok && hipMemcpyAsync(sn->A, P.L.st.ps_A, sizeof(int64_t) * pop, d2h, s) == hipSuccess;
+        ok = ok && hipMemcpyAsync(sn->S, P.L.st.ps_S, sizeof(int64_t) * pop, d2h, s) == hipSuccess;
+        ok = ok && hipStreamSynchronize(s) == hipSuccess;
+        if (!ok) {
+            hpmocd_snapshot_free(sn);
+            return HPMOCD_ERR_HIP;
+        }
+        *out = sn;
+        return HPMOCD_OK;
+    });
 }
 
 int hpmocd_resume(const hpmocd_graph *G, const hpmocd_params *p, const hpmocd_snapshot *sn,
                   void *ws, size_t ws_bytes, void *stream, hpmocd_front **out)
 {
-    if (!G || !p || !sn || !out || !ws || !sn->labels || !sn->A || !sn->S) return HPMOCD_ERR_ARG;
-    int rc = check_params(p);
-    if (rc) return rc;
-    const int32_t n = G->n, pop = p->pop_size, T = p->generations;
-    if (sn->n_nodes != n || sn->pop_size != pop || sn->g < 0 || sn->g > T) return HPMOCD_ERR_ARG;
-    // the snapshot belongs to this graph and these parameters (the generation count may grow)
-    const hpmocd_params &q = sn->params;
-    if (sn->graph_hash != G->hash || q.pop_size != pop || q.seed != p->seed ||
-        q.crossover_p != p->crossover_p || q.mutation_p != p->mutation_p ||
-        q.parents_per_child != p->parents_per_child)
-        return HPMOCD_ERR_ARG;
-    for (size_t i = 0; i < (size_t)pop * n; ++i)
-        if (sn->labels[i] < 0 || sn->labels[i] >= n) return HPMOCD_ERR_RANGE;
-    const int64_t m2 = G->m2;
-    std::vector<int32_t> ids(pop);
-    for (int32_t i = 0; i < pop; ++i) {
-        if (sn->A[i] < 0 || sn->A[i] > m2 || sn->S[i] < 0 || sn->S[i] > m2 * m2)
-            return HPMOCD_ERR_RANGE;
-        ids[i] = i;  // member i lives in column i of the committed pool
-    }
-    if ((rc = check_device(G))) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    DrainOnExit drain{s};
-    Batch B;
-    if ((rc = B.setup(&G, 1, p, ws, ws_bytes, Tuning{}, false, s))) return rc;
-    Pop &P = B.pops[0];
-    P.cur = 0;
-    const DevState &st = P.L.st;
-    const int32_t gen = sn->g + 1;  // the device generation counter after selection of g
-    const hipMemcpyKind h2d = hipMemcpyHostToDevice;
-    HIP_TRY(hipMemcpyAsync(P.L.C, sn->labels, sizeof(int32_t) * (size_t)pop * n, h2d, s));
-    HIP_TRY(launch_transpose_in(P.L.C, n, pop, P.c.ld, P.L.pool[0], nullptr, s));  // checked above
-    HIP_TRY(hipMemcpyAsync(st.ps_id, ids.data(), sizeof(int32_t) * pop, h2d, s));
-    HIP_TRY(hipMemcpyAsync(st.ps_A, sn->A, sizeof(int64_t) * pop, h2d, s));
-    HIP_TRY(hipMemcpyAsync(st.ps_S, sn->S, sizeof(int64_t) * pop, h2d, s));
-    // f1, f2 from A, S by the kernels' own divisions (eq. objectives)
-    HIP_TRY(launch_finalize(m2, pop, (const unsigned long long *)st.ps_A,
-                            (const unsigned long long *)st.ps_S, st.ps_f1, st.ps_f2, s));
-    HIP_TRY(hipMemcpyAsync(st.gen, &gen, sizeof(int32_t), h2d, s));
-    // re-evaluate the members with the fitness kernels (eq. objectives) through a one-item
-    // table in the init table's place (no initialisation runs on resume): the stored A and S
-    // must be those of the stored labels
-    {
-        Item ev = P.item(ITEM_PARITY0);
-        ev.lab = P.L.pool[0];
-        Meta mv;
-        if ((rc = mv.upload(&ev, 1, (void *)B.meta[0].items, s))) return rc;
-        HIP_TRY(mv.launch(K_CLEAR, s));
-        HIP_TRY(mv.one(ONE_ZERO_ACC, s));
-        HIP_TRY(launch_fitness_kinds(mv, s, nullptr));
-        std::vector<int64_t> A(pop), S(pop);
-        HIP_TRY(copy_small({{A.data(), ev.fit_A, sizeof(int64_t) * pop},
-                            {S.data(), ev.fit_S, sizeof(int64_t) * pop}}, s));
-        for (int32_t i = 0; i < pop; ++i)
-            if (A[i] != sn->A[i] || S[i] != sn->S[i]) return HPMOCD_ERR_ARG;
-    }
-    HIP_TRY(B.meta[1].launch(K_CLEAR, s));  // the plain histogram plane starts at zero
-    if ((rc = B.generations(sn->g + 1, T, s, s != nullptr, nullptr, nullptr, nullptr, false)))
+    return c_guard([&]() -> int {
+        if (!G || !p || !sn || !out || !ws || !sn->labels || !sn->A || !sn->S) return HPMOCD_ERR_ARG;
+        int rc = check_params(p);
+        if (rc) return rc;
+        const int32_t n = G->n, pop = p->pop_size, T = p->generations;
+        if (sn->n_nodes != n || sn->pop_size != pop || sn->g < 0 || sn->g > T) return HPMOCD_ERR_ARG;
+        // the snapshot belongs to this graph and these parameters (the generation count may grow)
+        const hpmocd_params &q = sn->params;
+        if (sn->graph_hash != G->hash || q.pop_size != pop || q.seed != p->seed ||
+            q.crossover_p != p->crossover_p || q.mutation_p != p->mutation_p ||
+            q.parents_per_child != p->parents_per_child)
+            return HPMOCD_ERR_ARG;
+        for (size_t i = 0; i < (size_t)pop * n; ++i)
+            if (sn->labels[i] < 0 || sn->labels[i] >= n) return HPMOCD_ERR_RANGE;
+        const int64_t m2 = G->m2;
+        std::vector<int32_t> ids(pop);
+        for (int32_t i = 0; i < pop; ++i) {
+            if (sn->A[i] < 0 || sn->A[i] > m2 || sn->S[i] < 0 || sn->S[i] > m2 * m2)
+                return HPMOCD_ERR_RANGE;
+            ids[i] = i;  // member i lives in column i of the committed pool
+        }
+        if ((rc = check_device(G))) return rc;
+        hipStream_t s = (hipStream_t)stream;
+        DrainOnExit drain{s};
+        Batch B;
+        if ((rc = B.setup(&G, 1, p, ws, ws_bytes, Tuning{}, false, s))) return rc;
+        Pop &P = B.pops[0];
+        P.cur = 0;
+        const DevState &st = P.L.st;
+        const int32_t gen = sn->g + 1;  // the device generation counter after selection of g
+        const hipMemcpyKind h2d = hipMemcpyHostToDevice;
+        HIP_TRY(hipMemcpyAsync(P.L.C, sn->labels, sizeof(int32_t) * (size_t)pop * n, h2d, s));
+        HIP_TRY(launch_transpose_in(P.L.C, n, pop, P.c.ld, P.L.pool[0], nullptr, s));  // checked above
+        HIP_TRY(hipMemcpyAsync(st.ps_id, ids.data(), sizeof(int32_t) * pop, h2d, s));
+        HIP_TRY(hipMemcpyAsync(st.ps_A, sn->A, sizeof(int64_t) * pop, h2d, s));
+        HIP_TRY(hipMemcpyAsync(st.ps_S, sn->S, sizeof(int64_t) * pop, h2d, s));
+        // f1, f2 from A, S by the kernels' own divisions (eq. objectives)
+        HIP_TRY(launch_finalize(m2, pop, (const unsigned long long *)st.ps_A,
+                                (const unsigned long long *)st.ps_S, st.ps_f1, st.ps_f2, s));
+        HIP_TRY(hipMemcpyAsync(st.gen, &gen, sizeof(int32_t), h2d, s));
+        // re-evaluate the members with the fitness kernels (eq. objectives) through a one-item
+        // table in the init table's place (no initialisation runs on resume): the stored A and S
+        // must be those of the stored labels
+        {
+            Item ev = P.item(ITEM_PARITY0);
+            ev.lab = P.L.pool[0];
+            Meta mv;
+            if ((rc = mv.upload(&ev, 1, (void *)B.meta[0].items, s))) return rc;
+            HIP_TRY(mv.launch(K_CLEAR, s));
+            HIP_TRY(mv.one(ONE_ZERO_ACC, s));
+            HIP_TRY(launch_fitness_kinds(mv, s, nullptr));
+            std::vector<int64_t> A(pop), S(pop);
+            HIP_TRY(copy_small({{A.data(), ev.fit_A, sizeof(int64_t) * pop},
+                                {S.data(), ev.fit_S, sizeof(int64_t) * pop}}, s));
+            for (int32_t i = 0; i < pop; ++i)
+                if (A[i] != sn->A[i] || S[i] != sn->S[i]) return HPMOCD_ERR_ARG;
+        }
+        HIP_TRY(B.meta[1].launch(K_CLEAR, s));  // the plain histogram plane starts at zero
+        if ((rc = B.generations(sn->g + 1, T, s, s != nullptr, nullptr, nullptr, nullptr, false)))
+            return rc;
+        HIP_TRY(B.meta[1 + P.cur].one(ONE_FINAL, s));
+        rc = extract_front(P, s, out);  // synchronises s: the host arrays above outlive the copies
         return rc;
-    HIP_TRY(B.meta[1 + P.cur].one(ONE_FINAL, s));
-    rc = extract_front(P, s, out);  // synchronises s: the host arrays above outlive the copies
-    return rc;
+    });
 }
 
 }  // extern "C"
@@ -1528,31 +1544,35 @@ extern "C" {
 // ---------------------------------------------------------------------------------------
 int hpmocd_eval_workspace_size(const hpmocd_graph *g, int32_t n_ind, size_t *bytes)
 {
-    if (!g || !bytes || n_ind < 1) return HPMOCD_ERR_ARG;
-    const int32_t ld = round16(n_ind);
-    const Tuning t;
-    const HistPlan hp = hist_plan(g->n, n_ind, g->max_deg, t.hist_min_log2, t.hist_rbits,
-                                  t.hist_narrow != 0);
-    size_t b = align_up((size_t)g->n * ld * 4);  // transposed labels
-    b += hp.enabled ? align_up(hp.entries * 4) + align_up(hp.offsets * 4) : align_up((size_t)g->n * ld * 4);
-    b += 2 * align_up(8 * (size_t)n_ind) + 2 * align_up(8 * (size_t)n_ind);
-    b += align_up(sizeof(int32_t));  // out-of-range label flag
-    b += meta_bytes(1);
-    *bytes = b;
-    return HPMOCD_OK;
+    return c_guard([&]() -> int {
+        if (!g || !bytes || n_ind < 1) return HPMOCD_ERR_ARG;
+        const int32_t ld = round16(n_ind);
+        const Tuning t;
+        const HistPlan hp = hist_plan(g->n, n_ind, g->max_deg, t.hist_min_log2, t.hist_rbits,
+                                      t.hist_narrow != 0);
+        size_t b = align_up((size_t)g->n * ld * 4);  // transposed labels
+        b += hp.enabled ? align_up(hp.entries * 4) + align_up(hp.offsets * 4) : align_up((size_t)g->n * ld * 4);
+        b += 2 * align_up(8 * (size_t)n_ind) + 2 * align_up(8 * (size_t)n_ind);
+        b += align_up(sizeof(int32_t));  // out-of-range label flag
+        b += meta_bytes(1);
+        *bytes = b;
+        return HPMOCD_OK;
+    });
 }
 
 int hpmocd_eval(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, void *ws,
                 size_t ws_bytes, void *stream, int64_t *A, int64_t *S, double *f1, double *f2,
                 double *kernel_ms)
 {
-    if (!G || !d_labels || n_ind < 1 || !ws || !A || !S || !f1 || !f2) return HPMOCD_ERR_ARG;
-    int rc = check_device(G);
-    if (rc) return rc;
-    size_t need = 0;
-    hpmocd_eval_workspace_size(G, n_ind, &need);
-    if (ws_bytes < need) return HPMOCD_ERR_WORKSPACE;
-    return eval_on(G, d_labels, n_ind, ws, (hipStream_t)stream, A, S, f1, f2, kernel_ms);
+    return c_guard([&]() -> int {
+        if (!G || !d_labels || n_ind < 1 || !ws || !A || !S || !f1 || !f2) return HPMOCD_ERR_ARG;
+        int rc = check_device(G);
+        if (rc) return rc;
+        size_t need = 0;
+        hpmocd_eval_workspace_size(G, n_ind, &need);
+        if (ws_bytes < need) return HPMOCD_ERR_WORKSPACE;
+        return eval_on(G, d_labels, n_ind, ws, (hipStream_t)stream, A, S, f1, f2, kernel_ms);
+    });
 }
 
 }  // extern "C"

@@ -342,63 +342,70 @@ void hpmocd_server::run()
             if (f.valid) return true;
         return false;
     };
-    for (;;) {
-        std::vector<Request *> admitted;
-        {
-            std::unique_lock<std::mutex> lk(mu);
-            cv_work.wait(lk, [&] {
-                return stop || !queue.empty() || !active.empty() || any_in_flight();
-            });
-            if (stop || broken) break;
-            // resident requests cancelled since the last launch: the steps in flight may still
-            // use their memory, so it is released when the newest of them completes
-            Flight &newest = flight[(cur + SERVER_DEPTH - 1) % SERVER_DEPTH];
-            for (Request *r : active)
-                if (r->cancel) {
-                    if (newest.valid)
-                        newest.released.push_back(r);
-                    else
-                        release(r, HPMOCD_ERR_CANCELLED);
+    try {
+        for (;;) {
+            std::vector<Request *> admitted;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_work.wait(lk, [&] {
+                    return stop || !queue.empty() || !active.empty() || any_in_flight();
+                });
+                if (stop || broken) break;
+                // resident requests cancelled since the last launch: the steps in flight may still
+                // use their memory, so it is released when the newest of them completes
+                Flight &newest = flight[(cur + SERVER_DEPTH - 1) % SERVER_DEPTH];
+                for (Request *r : active)
+                    if (r->cancel) {
+                        if (newest.valid)
+                            newest.released.push_back(r);
+                        else
+                            release(r, HPMOCD_ERR_CANCELLED);
+                    }
+                active.erase(std::remove_if(active.begin(), active.end(),
+                                            [](Request *r) { return r->cancel; }),
+                             active.end());
+                cv_done.notify_all();
+                while (!queue.empty() && (int32_t)active.size() < cfg.max_active &&
+                       !(fifo && !active.empty())) {
+                    Request *r = queue.front();
+                    if (used + r->bytes > cfg.hbm_budget) break;  // arrival order: no overtaking
+                    admitted.reserve(admitted.size() + 1);  // may throw: r is still queued
+                    active.reserve(active.size() + 1);
+                    size_t off = 0;
+                    if (!alloc.alloc(r->bytes, &off)) break;
+                    queue.pop_front();
+                    r->off = off;
+                    used += r->bytes;
+                    r->state = HPMOCD_REQ_RUNNING;
+                    r->t_admit = now();
+                    active.push_back(r);
+                    admitted.push_back(r);
+                    ++stats.admitted;
                 }
-            active.erase(std::remove_if(active.begin(), active.end(),
-                                        [](Request *r) { return r->cancel; }),
-                         active.end());
-            cv_done.notify_all();
-            while (!queue.empty() && (int32_t)active.size() < cfg.max_active &&
-                   !(fifo && !active.empty())) {
-                Request *r = queue.front();
-                if (used + r->bytes > cfg.hbm_budget) break;  // arrival order: no overtaking
-                size_t off = 0;
-                if (!alloc.alloc(r->bytes, &off)) break;
-                queue.pop_front();
-                r->off = off;
-                used += r->bytes;
-                r->state = HPMOCD_REQ_RUNNING;
-                r->t_admit = now();
-                active.push_back(r);
-                admitted.push_back(r);
-                ++stats.admitted;
+                stats.peak_active = std::max<int32_t>(stats.peak_active, (int32_t)active.size());
+                stats.peak_bytes = std::max<int64_t>(stats.peak_bytes, (int64_t)used);
             }
-            stats.peak_active = std::max<int32_t>(stats.peak_active, (int32_t)active.size());
-            stats.peak_bytes = std::max<int64_t>(stats.peak_bytes, (int64_t)used);
+            const double t0 = now();
+            int rc = HPMOCD_OK;
+            bool launched = false;
+            if (!active.empty()) {
+                rc = fifo ? run_fifo(active.front()) : launch(flight[cur], cur, admitted);
+                launched = true;
+            }
+            Flight &oldest = flight[(cur + 1) % SERVER_DEPTH];
+            if (!rc && oldest.valid) rc = complete(oldest);
+            std::lock_guard<std::mutex> lk(mu);
+            stats.busy_s += now() - t0;
+            if (launched) ++stats.steps;
+            if (rc) {
+                broken = rc;
+                break;
+            }
+            cur = (cur + 1) % SERVER_DEPTH;
         }
-        const double t0 = now();
-        int rc = HPMOCD_OK;
-        bool launched = false;
-        if (!active.empty()) {
-            rc = fifo ? run_fifo(active.front()) : launch(flight[cur], cur, admitted);
-            launched = true;
-        }
-        Flight &oldest = flight[(cur + 1) % SERVER_DEPTH];
-        if (!rc && oldest.valid) rc = complete(oldest);
+    } catch (...) {  // host resources ran out (an allocation): the server stops like on a failure
         std::lock_guard<std::mutex> lk(mu);
-        stats.busy_s += now() - t0;
-        if (launched) ++stats.steps;
-        if (rc) {
-            broken = rc;
-            break;
-        }
-        cur = (cur + 1) % SERVER_DEPTH;
+        if (!broken) broken = HPMOCD_ERR_NOMEM;
     }
     // shutdown or failure: settle what was launched, then nothing queued will run
     (void)hipStreamSynchronize(up_stream);
@@ -429,170 +436,182 @@ extern "C" {
 int hpmocd_server_create(const hpmocd_server_config *cfg, void *d_arena, size_t arena_bytes,
                          void *stream, hpmocd_server **out)
 {
-    if (!cfg || !d_arena || !out) return HPMOCD_ERR_ARG;
-    if (cfg->max_active < 1 || cfg->max_active > HPMOCD_SERVER_MAX_ACTIVE) return HPMOCD_ERR_ARG;
-    if (cfg->parents_per_child < 1 || cfg->parents_per_child > HPMOCD_MAX_PARENTS)
-        return HPMOCD_ERR_ARG;
-    if (cfg->flags & ~HPMOCD_SERVER_FIFO) return HPMOCD_ERR_ARG;
-    const size_t over = hpmocd_server_arena_overhead(cfg->max_active);
-    if (arena_bytes < over || arena_bytes - over < cfg->hbm_budget || cfg->hbm_budget == 0)
-        return HPMOCD_ERR_WORKSPACE;
-    if ((uintptr_t)d_arena % 256) return HPMOCD_ERR_ARG;
-    hpmocd_server *s = new (std::nothrow) hpmocd_server;
-    if (!s) return HPMOCD_ERR_NOMEM;
-    s->cfg = *cfg;
-    // resident requests share every launch, like a batch (FIFO runs go through run_batch alone)
-    s->tuning = default_tuning(cfg->max_active);
-    s->arena = (char *)d_arena;
-    s->table_bytes = over;
-    s->stream = (hipStream_t)stream;
-    s->epoch = Clock::now();
-    bool ok = hipGetDevice(&s->device) == hipSuccess && s->fork.init() == HPMOCD_OK;
-    ok = ok && hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipStreamCreateWithFlags(&s->up_stream, hipStreamNonBlocking) == hipSuccess;
-    for (hipEvent_t &e : s->up_done)
-        ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
-    for (Flight &f : s->flight)
-        ok = ok && hipEventCreateWithFlags(&f.done, hipEventDisableTiming) == hipSuccess;
-    // staging per in-flight step: a third for the step's new graphs and tables, two thirds
-    // for the fronts it finishes; copies that do not fit use pageable memory
-    const size_t stage = cfg->host_stage_bytes ? cfg->host_stage_bytes : SERVER_STAGE_DEFAULT;
-    for (int i = 0; i < SERVER_DEPTH; ++i)
-        for (Pinned *p : {&s->up_stage[i], &s->front_stage[i]}) {
-            const bool front = p == &s->front_stage[i];
-            const size_t bytes = (front ? 2 * (stage / 3) : stage / 3) / 256 * 256;
-            if (bytes < SERVER_STAGE_MIN) continue;
-            p->size = bytes;
-            ok = ok && hipHostMalloc((void **)&p->base, p->size, hipHostMallocDefault) == hipSuccess;
+    return c_guard([&]() -> int {
+        if (!cfg || !d_arena || !out) return HPMOCD_ERR_ARG;
+        if (cfg->max_active < 1 || cfg->max_active > HPMOCD_SERVER_MAX_ACTIVE) return HPMOCD_ERR_ARG;
+        if (cfg->parents_per_child < 1 || cfg->parents_per_child > HPMOCD_MAX_PARENTS)
+            return HPMOCD_ERR_ARG;
+        if (cfg->flags & ~HPMOCD_SERVER_FIFO) return HPMOCD_ERR_ARG;
+        const size_t over = hpmocd_server_arena_overhead(cfg->max_active);
+        if (arena_bytes < over || arena_bytes - over < cfg->hbm_budget || cfg->hbm_budget == 0)
+            return HPMOCD_ERR_WORKSPACE;
+        if ((uintptr_t)d_arena % 256) return HPMOCD_ERR_ARG;
+        hpmocd_server *s = new (std::nothrow) hpmocd_server;
+        if (!s) return HPMOCD_ERR_NOMEM;
+        s->cfg = *cfg;
+        // resident requests share every launch, like a batch (FIFO runs go through run_batch alone)
+        s->tuning = default_tuning(cfg->max_active);
+        s->arena = (char *)d_arena;
+        s->table_bytes = over;
+        s->stream = (hipStream_t)stream;
+        s->epoch = Clock::now();
+        bool ok = hipGetDevice(&s->device) == hipSuccess && s->fork.init() == HPMOCD_OK;
+        ok = ok && hipStreamCreateWithFlags(&s->copy_stream, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipStreamCreateWithFlags(&s->up_stream, hipStreamNonBlocking) == hipSuccess;
+        for (hipEvent_t &e : s->up_done)
+            ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+        for (Flight &f : s->flight)
+            ok = ok && hipEventCreateWithFlags(&f.done, hipEventDisableTiming) == hipSuccess;
+        // staging per in-flight step: a third for the step's new graphs and tables, two thirds
+        // for the fronts it finishes; copies that do not fit use pageable memory
+        const size_t stage = cfg->host_stage_bytes ? cfg->host_stage_bytes : SERVER_STAGE_DEFAULT;
+        for (int i = 0; i < SERVER_DEPTH; ++i)
+            for (Pinned *p : {&s->up_stage[i], &s->front_stage[i]}) {
+                const bool front = p == &s->front_stage[i];
+                const size_t bytes = (front ? 2 * (stage / 3) : stage / 3) / 256 * 256;
+                if (bytes < SERVER_STAGE_MIN) continue;
+                p->size = bytes;
+                ok = ok && hipHostMalloc((void **)&p->base, p->size, hipHostMallocDefault) == hipSuccess;
+            }
+        if (!ok) {
+            delete s;
+            return HPMOCD_ERR_HIP;
         }
-    if (!ok) {
-        delete s;
-        return HPMOCD_ERR_HIP;
-    }
-    // block offsets are relative to the arena start; the tables come first
-    s->alloc.reset(0);
-    s->alloc.release(over, arena_bytes - over);
-    try {
-        s->worker = std::thread([s] { s->run(); });
-    } catch (...) {
-        delete s;
-        return HPMOCD_ERR_NOMEM;
-    }
-    *out = s;
-    return HPMOCD_OK;
+        // block offsets are relative to the arena start; the tables come first
+        s->alloc.reset(0);
+        s->alloc.release(over, arena_bytes - over);
+        try {
+            s->worker = std::thread([s] { s->run(); });
+        } catch (...) {
+            delete s;
+            return HPMOCD_ERR_NOMEM;
+        }
+        *out = s;
+        return HPMOCD_OK;
+    });
 }
 
 int hpmocd_server_submit(hpmocd_server *s, int32_t n, const int32_t *row_ptr, const int32_t *col,
                          const hpmocd_params *p, int64_t *ticket, size_t *device_bytes)
 {
-    if (!s || !ticket) return HPMOCD_ERR_ARG;
-    int rc = check_params(p);
-    if (rc) return rc;
-    if (p->parents_per_child != s->cfg.parents_per_child) return HPMOCD_ERR_ARG;
-    std::unique_ptr<Request> r(new (std::nothrow) Request);
-    if (!r) return HPMOCD_ERR_NOMEM;
-    if ((rc = prepare_graph(n, row_ptr, col, &r->hg))) return rc;
-    r->p = *p;
-    r->graph_bytes = align_up(graph_block_bytes(r->hg.n, r->hg.m2, (int32_t)r->hg.small.size(),
-                                                (int32_t)r->hg.large.size()));
-    if (s->cfg.flags & HPMOCD_SERVER_FIFO) {  // a plain run's workspace
-        hpmocd_graph shape;
-        shape.n = r->hg.n;
-        shape.max_deg = r->hg.max_deg;
-        const hpmocd_graph *gp = &shape;
-        r->bytes = r->graph_bytes + align_up(batch_workspace(&gp, 1, p, false));
-    } else {
-        r->bytes = r->graph_bytes +
-                   align_up(carve_run(nullptr, r->hg.n, p->pop_size, p->parents_per_child,
-                                      r->hg.max_deg, s->tuning, false)
-                                .bytes);
-    }
-    if (r->bytes > s->cfg.hbm_budget) return HPMOCD_ERR_BUDGET;
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->broken) return s->broken;
-    if (s->stop) return HPMOCD_ERR_CANCELLED;
-    r->ticket = s->next_ticket++;
-    r->t_submit = s->now();
-    *ticket = r->ticket;
-    if (device_bytes) *device_bytes = r->bytes;
-    s->queue.push_back(r.get());
-    s->reqs[r->ticket] = std::move(r);
-    s->cv_work.notify_one();
-    return HPMOCD_OK;
+    return c_guard([&]() -> int {
+        if (!s || !ticket) return HPMOCD_ERR_ARG;
+        int rc = check_params(p);
+        if (rc) return rc;
+        if (p->parents_per_child != s->cfg.parents_per_child) return HPMOCD_ERR_ARG;
+        std::unique_ptr<Request> r(new (std::nothrow) Request);
+        if (!r) return HPMOCD_ERR_NOMEM;
+        if ((rc = prepare_graph(n, row_ptr, col, &r->hg))) return rc;
+        r->p = *p;
+        r->graph_bytes = align_up(graph_block_bytes(r->hg.n, r->hg.m2, (int32_t)r->hg.small.size(),
+                                                    (int32_t)r->hg.large.size()));
+        if (s->cfg.flags & HPMOCD_SERVER_FIFO) {  // a plain run's workspace
+            hpmocd_graph shape;
+            shape.n = r->hg.n;
+            shape.max_deg = r->hg.max_deg;
+            const hpmocd_graph *gp = &shape;
+            r->bytes = r->graph_bytes + align_up(batch_workspace(&gp, 1, p, false));
+        } else {
+            r->bytes = r->graph_bytes +
+                       align_up(carve_run(nullptr, r->hg.n, p->pop_size, p->parents_per_child,
+                                          r->hg.max_deg, s->tuning, false)
+                                    .bytes);
+        }
+        if (r->bytes > s->cfg.hbm_budget) return HPMOCD_ERR_BUDGET;
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->broken) return s->broken;
+        if (s->stop) return HPMOCD_ERR_CANCELLED;
+        r->ticket = s->next_ticket++;
+        r->t_submit = s->now();
+        *ticket = r->ticket;
+        if (device_bytes) *device_bytes = r->bytes;
+        s->queue.push_back(r.get());
+        s->reqs[r->ticket] = std::move(r);
+        s->cv_work.notify_one();
+        return HPMOCD_OK;
+    });
 }
 
 int hpmocd_server_poll(hpmocd_server *s, int64_t ticket, int32_t *state)
 {
-    if (!s || !state) return HPMOCD_ERR_ARG;
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return HPMOCD_ERR_ARG;
-    *state = it->second->state;
-    return HPMOCD_OK;
+    return c_guard([&]() -> int {
+        if (!s || !state) return HPMOCD_ERR_ARG;
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return HPMOCD_ERR_ARG;
+        *state = it->second->state;
+        return HPMOCD_OK;
+    });
 }
 
 int hpmocd_server_wait(hpmocd_server *s, int64_t ticket, double timeout_s, hpmocd_front **out,
                        hpmocd_request_info *info)
 {
-    if (!s || !out) return HPMOCD_ERR_ARG;
-    std::unique_lock<std::mutex> lk(s->mu);
-    if (s->reqs.find(ticket) == s->reqs.end()) return HPMOCD_ERR_ARG;
-    // looked up again at every wake-up: another thread's wait on the same ticket may have
-    // consumed it meanwhile
-    auto settled = [&] {
-        auto i = s->reqs.find(ticket);
-        return i == s->reqs.end() || i->second->state == HPMOCD_REQ_DONE;
-    };
-    if (timeout_s < 0) {
-        s->cv_done.wait(lk, settled);
-    } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), settled)) {
-        return HPMOCD_ERR_TIMEOUT;
-    }
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return HPMOCD_ERR_ARG;
-    Request *r = it->second.get();
-    const int st = r->status;
-    if (st == HPMOCD_OK) {
-        *out = r->front;
-        r->front = nullptr;
-        if (info) {
-            info->submit_s = r->t_submit;
-            info->admit_s = r->t_admit;
-            info->done_s = r->t_done;
-            info->device_bytes = (int64_t)r->bytes;
-            info->steps = r->steps;
-            info->max_mix = r->max_mix;
+    return c_guard([&]() -> int {
+        if (!s || !out) return HPMOCD_ERR_ARG;
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (s->reqs.find(ticket) == s->reqs.end()) return HPMOCD_ERR_ARG;
+        // looked up again at every wake-up: another thread's wait on the same ticket may have
+        // consumed it meanwhile
+        auto settled = [&] {
+            auto i = s->reqs.find(ticket);
+            return i == s->reqs.end() || i->second->state == HPMOCD_REQ_DONE;
+        };
+        if (timeout_s < 0) {
+            s->cv_done.wait(lk, settled);
+        } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), settled)) {
+            return HPMOCD_ERR_TIMEOUT;
         }
-    }
-    hpmocd_front_free(r->front);
-    s->reqs.erase(it);
-    return st;
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return HPMOCD_ERR_ARG;
+        Request *r = it->second.get();
+        const int st = r->status;
+        if (st == HPMOCD_OK) {
+            *out = r->front;
+            r->front = nullptr;
+            if (info) {
+                info->submit_s = r->t_submit;
+                info->admit_s = r->t_admit;
+                info->done_s = r->t_done;
+                info->device_bytes = (int64_t)r->bytes;
+                info->steps = r->steps;
+                info->max_mix = r->max_mix;
+            }
+        }
+        hpmocd_front_free(r->front);
+        s->reqs.erase(it);
+        return st;
+    });
 }
 
 int hpmocd_server_cancel(hpmocd_server *s, int64_t ticket)
 {
-    if (!s) return HPMOCD_ERR_ARG;
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return HPMOCD_ERR_ARG;
-    Request *r = it->second.get();
-    if (r->state == HPMOCD_REQ_QUEUED) {
-        s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
-        s->finish(r, HPMOCD_ERR_CANCELLED);
-        s->cv_done.notify_all();
-    } else if (r->state == HPMOCD_REQ_RUNNING) {
-        r->cancel = true;
-        s->cv_work.notify_one();
-    }
-    return HPMOCD_OK;
+    return c_guard([&]() -> int {
+        if (!s) return HPMOCD_ERR_ARG;
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return HPMOCD_ERR_ARG;
+        Request *r = it->second.get();
+        if (r->state == HPMOCD_REQ_QUEUED) {
+            s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
+            s->finish(r, HPMOCD_ERR_CANCELLED);
+            s->cv_done.notify_all();
+        } else if (r->state == HPMOCD_REQ_RUNNING) {
+            r->cancel = true;
+            s->cv_work.notify_one();
+        }
+        return HPMOCD_OK;
+    });
 }
 
 int hpmocd_server_stats_get(hpmocd_server *s, hpmocd_server_stats *out)
 {
-    if (!s || !out) return HPMOCD_ERR_ARG;
-    std::lock_guard<std::mutex> lk(s->mu);
-    *out = s->stats;
-    return HPMOCD_OK;
+    return c_guard([&]() -> int {
+        if (!s || !out) return HPMOCD_ERR_ARG;
+        std::lock_guard<std::mutex> lk(s->mu);
+        *out = s->stats;
+        return HPMOCD_OK;
+    });
 }
 
 void hpmocd_server_destroy(hpmocd_server *s)
