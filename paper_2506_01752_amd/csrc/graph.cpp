@@ -43,12 +43,25 @@ int prepare_graph(int32_t n, const int32_t *row_ptr, const int32_t *col, HostGra
         for (int32_t e = rs + 1; e < re; ++e)
             if (c[e] == c[e - 1]) return HPMOCD_ERR_DUP_EDGE;
     }
-    for (int32_t v = 0; v < n; ++v)
-        for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-            const int32_t u = c[e];
-            if (!std::binary_search(c.begin() + row_ptr[u], c.begin() + row_ptr[u + 1], v))
-                return HPMOCD_ERR_CSR_ASYM;
-        }
+    // Symmetry: with every row sorted and free of repeats, the arcs are symmetric exactly when
+    // the transpose equals them. Each node's in-degree must equal its degree; the transpose's
+    // rows are then filled by walking the sources in ascending order, which leaves every row
+    // sorted, and compared with the rows as given (a sequential pass instead of one binary
+    // search into a random row per arc).
+    try {
+        std::vector<int32_t> pos(row_ptr, row_ptr + n);
+        for (int64_t e = 0; e < m2; ++e) ++pos[c[e]];
+        for (int32_t u = 0; u < n; ++u)
+            if (pos[u] != row_ptr[u + 1]) return HPMOCD_ERR_CSR_ASYM;  // in-degree != degree
+        std::copy(row_ptr, row_ptr + n, pos.begin());
+        std::vector<int32_t> t((size_t)m2);
+        for (int32_t v = 0; v < n; ++v)
+            for (int32_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) t[pos[c[e]]++] = v;
+        if (std::memcmp(t.data(), c.data(), sizeof(int32_t) * (size_t)m2) != 0)
+            return HPMOCD_ERR_CSR_ASYM;
+    } catch (...) {
+        return HPMOCD_ERR_NOMEM;
+    }
     // upper arcs (u > v) for the fitness scan, and node classes for the mutation kernels
     // (counting sort by degree)
     try {
@@ -78,12 +91,13 @@ int prepare_graph(int32_t n, const int32_t *row_ptr, const int32_t *col, HostGra
     h.n = n;
     h.m2 = m2;
     h.max_deg = max_deg;
-    for (int k = 0; k < N_DEG_CLASSES; ++k) {
-        int32_t e = 0;
-        for (int32_t v : h.small)
-            if (row_ptr[v + 1] - row_ptr[v] <= DEG_CLASS_MAX[k]) ++e;
-        h.class_end[k] = e;
-    }
+    // small is in ascending degree order: each class ends where the degrees pass its bound
+    for (int k = 0; k < N_DEG_CLASSES; ++k)
+        h.class_end[k] = (int32_t)(std::upper_bound(h.small.begin(), h.small.end(), DEG_CLASS_MAX[k],
+                                                    [&](int32_t d, int32_t v) {
+                                                        return d < row_ptr[v + 1] - row_ptr[v];
+                                                    }) -
+                                   h.small.begin());
     h.large_max_deg = h.large.empty() ? 0 : row_ptr[h.large[0] + 1] - row_ptr[h.large[0]];
     // fingerprint: FNV-1a (Fowler, Noll, Vo), 64-bit, over the bytes of n, row_ptr and the
     // sorted col

@@ -51,8 +51,11 @@ def _csr(n, arcs):
 
 
 def test_validation_codes():
-    # asymmetric: arc 0->1 without 1->0
+    # asymmetric: arc 0->1 without 1->0 (node 0's in-degree differs from its degree)
     rp, col = _csr(3, [(0, 1), (1, 2), (2, 1)])
+    assert hp.graph_create_status(3, rp, col) == -2
+    # asymmetric with every in-degree equal to the degree: a directed 3-cycle
+    rp, col = _csr(3, [(0, 1), (1, 2), (2, 0)])
     assert hp.graph_create_status(3, rp, col) == -2
     # self-loop
     rp, col = _csr(2, [(0, 0), (0, 1), (1, 0)])
@@ -90,6 +93,36 @@ def test_valid_graphs_pass_validation():
     for v in range(g.n):
         col[g.row_ptr[v]:g.row_ptr[v + 1]] = col[g.row_ptr[v]:g.row_ptr[v + 1]][::-1]
     assert hp.graph_create_status(g.n, g.row_ptr, col) in (0, -9)
+
+
+def test_symmetry_check_on_random_graphs():
+    """Random simple graphs pass; the same graphs with one arc moved to another target
+    (in-degrees then differ) or with two arcs' targets swapped between two sources (every
+    in-degree and degree unchanged) are rejected as asymmetric."""
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        n = int(rng.integers(5, 60))
+        pairs = {(int(a), int(b)) for a, b in rng.integers(0, n, (3 * n, 2)) if a != b}
+        arcs = sorted(pairs | {(b, a) for a, b in pairs})
+        rp, col = _csr(n, arcs)
+        assert hp.graph_create_status(n, rp, col) in (0, -9), trial
+        out = {v: {b for a, b in arcs if a == v} for v in range(n)}
+        # one arc v->u moved to v->w (w not yet a neighbour of v)
+        v = next(x for x in range(n) if out[x] and len(out[x]) < n - 1)
+        u = min(out[v])
+        w = next(x for x in range(n) if x != v and x not in out[v])
+        moved = sorted((a, b) if (a, b) != (v, u) else (v, w) for a, b in arcs)
+        rp2, col2 = _csr(n, moved)
+        assert hp.graph_create_status(n, rp2, col2) == -2, trial
+        # two sources swap a target each: v->x, y->z become v->z, y->x
+        cand = [(a, b, c, d) for a, b in arcs for c, d in arcs
+                if a < c and b != d and d not in out[a] and b not in out[c] and d != a and b != c]
+        if not cand:
+            continue
+        a, b, c, d = cand[int(rng.integers(len(cand)))]
+        swapped = sorted({(x, y) for x, y in arcs if (x, y) not in ((a, b), (c, d))} | {(a, d), (c, b)})
+        rp3, col3 = _csr(n, swapped)
+        assert hp.graph_create_status(n, rp3, col3) == -2, trial
 
 
 def test_no_cpu_fallback_when_library_missing(tmp_path, monkeypatch):

@@ -51,6 +51,28 @@ def test_resume_equals_uninterrupted(hp, gname, k):
     assert same(plain, full)
 
 
+def test_snapshot_of_a_wide_population(hp):
+    """pop 300: the snapshot's 300 label rows leave the device through the extraction kernel
+    in three tiles of up to 128 rows (the last one partial). They equal the traced population,
+    resuming from them (which re-evaluates them) gives the uninterrupted front, and that
+    front is the oracle's."""
+    import torch
+
+    import oracle
+    s = torch.cuda.Stream()
+    g = synth.small_1k()
+    dg = hp.Graph(g.row_ptr, g.col)
+    p = hp.make_params(pop_size=300, generations=5, seed=23)
+    states = []
+    full = hp.run(dg, p, stream=s, on_generation=states.append)
+    snap = hp.run_to(dg, p, stop_gen=3, stream=s)
+    assert snap.labels.shape == (300, g.n)
+    assert np.array_equal(snap.labels, states[3].labels)
+    assert same(hp.resume(dg, snap, p, stream=s), full)
+    ref = oracle.run(g.row_ptr, g.col, pop_size=300, generations=5, seed=23, threads=4)
+    assert same(full, ref)
+
+
 def test_resume_rejects_bad_snapshots(hp):
     g = synth.small_1k()
     dg = hp.Graph(g.row_ptr, g.col)
