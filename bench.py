@@ -72,6 +72,22 @@ def measured_traffic(workload: str, pop: int):
     return measured_counter(workload, pop)
 
 
+def phase_rates(workload: str, pop: int, ms: dict):
+    """Per phase of a generation: counter bytes (committed summary, None when stale or
+    absent), duration and the physical rate against the HBM peak."""
+    gb = {"crossover": measured_counter(workload, pop, "crossover_traffic_GB"),
+          "mutation": measured_counter(workload, pop, "mutation_traffic_GB"),
+          "fitness step": measured_counter(workload, pop)}
+    out = {}
+    for k, t in ms.items():
+        b = gb.get(k)
+        b = int(round(b * 1e9)) if (b is not None and k != "fitness step") else b
+        out[k] = {"ms": t, "traffic_bytes": b,
+                  "GBps": (b / (t / 1e3) / 1e9) if (b and t > 0) else None,
+                  "frac_physical": (b / (t / 1e3) / 1e9 / HBM_PEAK_GBPS) if (b and t > 0) else None}
+    return out
+
+
 def copy_ceiling_gbps(mib: int = 1024, reps: int = 5) -> float:
     """Achievable HBM bandwidth on this device: a plain device-to-device copy of mib MiB
     (bytes read + bytes written per second, best of reps)."""
@@ -561,6 +577,8 @@ def main():
     achieved = bytes_launch / (eval_ms / 1e3) / 1e9
     traffic = measured_traffic(args.workload, pop)
     copy_gbps = copy_ceiling_gbps()
+    var_gen = sum(p["variation_ms"] for p in profs) / max(1, T * args.steps)
+    xo_gen = sum(p["crossover_ms"] for p in profs) / max(1, T * args.steps)
     out = {
         "metric": METRIC,
         "value": value,
@@ -590,8 +608,14 @@ def main():
         "end_to_end_edge_evals_per_s": edge_evals / wall if wall > 0 else None,
         "fitness_ms_per_population": eval_ms,
         "histogram_clear_ms_per_population": sweep_ms / launches,
-        "variation_ms_per_gen": sum(p["variation_ms"] for p in profs) / max(1, T * args.steps),
+        "variation_ms_per_gen": var_gen,
+        "crossover_ms_per_gen": xo_gen,
+        "mutation_ms_per_gen": var_gen - xo_gen,
         "select_ms_per_gen": sum(p["select_ms"] for p in profs) / max(1, T * args.steps),
+        # the other phases of a generation against the same committed counter summary: HBM
+        # bytes the counters saw each phase move, over its kernel-timing-pass duration
+        "generation_phases": phase_rates(args.workload, pop, {
+            "crossover": xo_gen, "mutation": var_gen - xo_gen, "fitness step": eval_ms}),
         "population_floor_GBps": population_floor_bytes(g.n, 2 * g.m, pop) / (eval_ms / 1e3) / 1e9,
         "roofline": {"bound": "hbm", "kernel": "fitness step (k_bin, then k_fitness beside k_hist)",
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",

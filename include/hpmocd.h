@@ -109,6 +109,7 @@ typedef struct {
     int32_t tune_hist_rbits;
     int32_t tune_hist_narrow;  /* 1: narrower histogram tiles and chunks on small graphs */
     double tune_probe_ms;      /* device time spent probing shapes (0 without autotuning) */
+    double crossover_ms;       /* the crossover kernels' part of variation_ms */
 } hpmocd_profile;
 
 #define HPMOCD_NO_GRAPH 1      /* launch each kernel (no hipGraph replay of the loop) */

@@ -90,7 +90,7 @@ class Profile(C.Structure):
                 ("tune_fit_target_waves", C.c_int32), ("tune_xo_target_blocks", C.c_int32),
                 ("tune_mut_target_items", C.c_int32), ("tune_hist_min_log2", C.c_int32),
                 ("tune_hist_rbits", C.c_int32), ("tune_hist_narrow", C.c_int32),
-                ("tune_probe_ms", C.c_double)]
+                ("tune_probe_ms", C.c_double), ("crossover_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

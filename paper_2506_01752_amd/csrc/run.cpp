@@ -334,7 +334,9 @@ hipError_t launch_generation(const Meta &m, hipStream_t s, const EventPair *ev, 
     if ((e = m.one(ONE_RANK_PARENTS, s)) != hipSuccess) return e;
     mark(0, true);
     mark(1, false);
+    mark(5, false);
     if ((e = m.launch(K_XO, s)) != hipSuccess) return e;
+    mark(5, true);
     if ((e = launch_mutation(m, s, fk)) != hipSuccess) return e;
     mark(1, true);
     mark(2, false);
@@ -1152,7 +1154,7 @@ int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_par
     EventSet evs;
     std::vector<std::vector<EventPair>> gen_events;
     if (time_kernels) {
-        gen_events.assign((size_t)T, std::vector<EventPair>(5));
+        gen_events.assign((size_t)T, std::vector<EventPair>(6));
         for (auto &v : gen_events)
             for (auto &pr : v) {
                 pr.a = evs.make();
@@ -1204,10 +1206,11 @@ int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_par
     if (prof) {
         HIP_TRY(hipEventRecord(e_end, s));
         HIP_TRY(hipEventSynchronize(e_end));
-        double fit_ms = 0, sweep_ms = 0, var_ms = 0, sel_ms = 0;
+        double fit_ms = 0, sweep_ms = 0, var_ms = 0, sel_ms = 0, xo_ms = 0;
         for (auto &ev : gen_events) {
             sel_ms += elapsed(ev[0].a, ev[0].b) + elapsed(ev[4].a, ev[4].b);
             var_ms += elapsed(ev[1].a, ev[1].b);
+            xo_ms += elapsed(ev[5].a, ev[5].b);
             fit_ms += elapsed(ev[2].a, ev[2].b);
             sweep_ms += elapsed(ev[3].a, ev[3].b);
         }
@@ -1218,6 +1221,7 @@ int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_par
         prof->fitness_ms = time_kernels ? fit_ms + elapsed(e_fit0, e_fit1) : 0.0;
         prof->sweep_ms = time_kernels ? sweep_ms : 0.0;
         prof->variation_ms = time_kernels ? var_ms : 0.0;
+        prof->crossover_ms = time_kernels ? xo_ms : 0.0;
         prof->select_ms = time_kernels ? sel_ms : 0.0;
         prof->fitness_launches = (int64_t)T + 1;
         prof->individual_evals = inds;
