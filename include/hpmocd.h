@@ -137,7 +137,10 @@ int hpmocd_workspace_size(const hpmocd_graph *g, const hpmocd_params *p, size_t 
  * crossover (Alg. 2) -> mutation (sec. 4.3.2) -> evaluation (eq. objectives) ->
  * environmental selection, then the first front and the Alg. 3 choice. d_workspace must be
  * device memory of at least hpmocd_workspace_size bytes; its contents on entry do not
- * matter. The front is returned in *out (free with hpmocd_front_free). */
+ * matter. The front is returned in *out (free with hpmocd_front_free). Runs called from
+ * several host threads at once take turns: the library runs one at a time per process (as
+ * are hpmocd_run_batch, hpmocd_run_to and hpmocd_resume); many graphs at once is what
+ * hpmocd_run_batch and the server are for. */
 int hpmocd_run(const hpmocd_graph *g, const hpmocd_params *p, void *d_workspace,
                size_t ws_bytes, void *stream, hpmocd_front **out);
 

@@ -1123,10 +1123,21 @@ static int autotune(const hpmocd_graph *const *graphs, int32_t count, const hpmo
     return HPMOCD_OK;
 }
 
+// Runs started from several host threads take turns (whole runs are serialised per
+// process): four threads each capturing, instantiating and replaying their own hipGraph at
+// once crashed the process with a segmentation fault, and no cause was found in this
+// library's code. Recursive: a trace callback may start a run of its own.
+std::recursive_mutex &run_mutex()
+{
+    static std::recursive_mutex mu;
+    return mu;
+}
+
 int run_batch(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_params *params,
               void *ws, size_t ws_bytes, void *stream, int flags, hpmocd_profile *prof,
               hpmocd_trace_fn trace, void *user, hpmocd_front **outs)
 {
+    std::lock_guard<std::recursive_mutex> serial(run_mutex());
     int rc = check_batch(graphs, count, params);
     if (rc) return rc;
     if (!ws || !outs) return HPMOCD_ERR_ARG;
@@ -1352,6 +1363,7 @@ int hpmocd_run_to(const hpmocd_graph *G, const hpmocd_params *p, int32_t stop_ge
         if (rc) return rc;
         if (stop_gen < 0 || stop_gen > p->generations) return HPMOCD_ERR_ARG;
         if ((rc = check_device(G))) return rc;
+        std::lock_guard<std::recursive_mutex> serial(run_mutex());
         hipStream_t s = (hipStream_t)stream;
         DrainOnExit drain{s};
         Batch B;
@@ -1401,6 +1413,7 @@ int hpmocd_resume(const hpmocd_graph *G, const hpmocd_params *p, const hpmocd_sn
         if (rc) return rc;
         const int32_t n = G->n, pop = p->pop_size, T = p->generations;
         if (sn->n_nodes != n || sn->pop_size != pop || sn->g < 0 || sn->g > T) return HPMOCD_ERR_ARG;
+        std::lock_guard<std::recursive_mutex> serial(run_mutex());
         // the snapshot belongs to this graph and these parameters (the generation count may grow)
         const hpmocd_params &q = sn->params;
         if (sn->graph_hash != G->hash || q.pop_size != pop || q.seed != p->seed ||
