@@ -1031,24 +1031,25 @@ int Batch::generations(int32_t first, int32_t last, hipStream_t s, bool use_grap
     return HPMOCD_OK;
 }
 
-// Autotuner: coordinate descent over the launch-shape knobs, each candidate timed on two
-// generations of this very batch (results discarded; every choice gives identical results,
+// Autotuner: coordinate descent over the launch-shape knobs, each candidate timed on one
+// generation of this very batch (results discarded; every choice gives identical results,
 // only the work decomposition changes).
 static int autotune(const hpmocd_graph *const *graphs, int32_t count, const hpmocd_params *params,
                     void *ws, size_t ws_bytes, hipStream_t s, Tuning *best, double *probe_ms)
 {
     std::vector<hpmocd_params> probe(params, params + count);
-    for (auto &p : probe) p.generations = 2;
+    for (auto &p : probe) p.generations = 1;
     EventSet evs;
     hipEvent_t a = evs.make(), b = evs.make();
     if (!a || !b) return HPMOCD_ERR_HIP;
     // The layout of the populations does not depend on the knobs (both histogram areas are
     // carved at their largest), so the initial populations are made once and every candidate
-    // then times two generations on whatever the previous one left: an even number of
-    // generations keeps the buffer parity, and the state always holds valid labels and ids.
+    // then times one generation on whatever the previous one left, at the buffer parity that
+    // left; the state always holds valid labels and ids.
     // Knob values often give the same launch shapes (e.g. every crossover target that rounds
     // to 16 nodes per workgroup): a candidate whose shapes were timed already is not run again.
     bool initialised = false;
+    int parity = 0;
     std::vector<std::pair<uint64_t, double>> seen;
     double spent = 0;  // GPU time of the candidates actually run
     auto time_it = [&](const Tuning &t, double *ms) -> int {
@@ -1079,9 +1080,11 @@ static int autotune(const hpmocd_graph *const *graphs, int32_t count, const hpmo
             HIP_TRY(launch_init_seq(bt.meta[0], s, &bt.fork));
             initialised = true;
         }
+        for (Pop &P : bt.pops) P.cur = parity;
         HIP_TRY(hipEventRecord(a, s));
-        rc = bt.generations(1, 2, s, false, nullptr, nullptr, nullptr, false);
+        rc = bt.generations(1, 1, s, false, nullptr, nullptr, nullptr, false);
         if (rc) return rc;
+        parity = bt.pops.empty() ? 0 : bt.pops[0].cur;
         HIP_TRY(hipEventRecord(b, s));
         HIP_TRY(hipEventSynchronize(b));
         *ms = elapsed(a, b);
