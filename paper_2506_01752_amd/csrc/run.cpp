@@ -297,9 +297,12 @@ Fork::~Fork()
     if (fork) (void)hipEventDestroy(fork);
 }
 
-// Mutation launches of one generation. With a fork: degree class <= 16 on s, 17-32 and 33-64
-// on the first side stream, the rest on the second (a split of their measured times at
-// |V| = 1M: about 1.2, 1.1 and 1.0 ms), joined back into s.
+// Mutation launches of one generation. With a fork, three branches joined back into s: degree
+// class <= 16 on s; 33-64, then 17-32 on the first side stream; the wave classes from the
+// highest degree down, then the large nodes, on the second. Longest items first within a
+// branch: a branch's last kernel then has short items to fill the chip with. At |V| = 1M,
+// pop 100, this order ran 337 generations/s against 329 for ascending order in each branch
+// (the fork as a whole: 287 with every class on s).
 static hipError_t launch_mutation(const Meta &m, hipStream_t s, const Fork *fk)
 {
     hipError_t e;
@@ -308,14 +311,16 @@ static hipError_t launch_mutation(const Meta &m, hipStream_t s, const Fork *fk)
             if ((e = m.launch((Kind)(K_MUT0 + k), s)) != hipSuccess) return e;
         return m.launch(K_MUTL, s);
     }
-    static const int group[N_DEG_CLASSES] = {0, 1, 1, 2, 2, 2, 2, 2};
+    static_assert(N_DEG_CLASSES == 8, "branch plan below covers classes 0-7");
+    static const int side0[] = {2, 1}, side1[] = {6, 5, 4, 3, 7};
     if ((e = hipEventRecord(fk->fork, s)) != hipSuccess) return e;
     for (int i = 0; i < 2; ++i)
         if ((e = hipStreamWaitEvent(fk->side[i], fk->fork, 0)) != hipSuccess) return e;
-    for (int k = 0; k < N_DEG_CLASSES; ++k) {
-        hipStream_t st = group[k] == 0 ? s : fk->side[group[k] - 1];
-        if ((e = m.launch((Kind)(K_MUT0 + k), st)) != hipSuccess) return e;
-    }
+    if ((e = m.launch(K_MUT0, s)) != hipSuccess) return e;
+    for (int k : side0)
+        if ((e = m.launch((Kind)(K_MUT0 + k), fk->side[0])) != hipSuccess) return e;
+    for (int k : side1)
+        if ((e = m.launch((Kind)(K_MUT0 + k), fk->side[1])) != hipSuccess) return e;
     if ((e = m.launch(K_MUTL, fk->side[1])) != hipSuccess) return e;
     for (int i = 0; i < 2; ++i) {
         if ((e = hipEventRecord(fk->join[i], fk->side[i])) != hipSuccess) return e;
