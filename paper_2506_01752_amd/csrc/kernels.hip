@@ -1141,15 +1141,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_mutate_lanes(Span sp, int cls)
         const int base = grp * G;
         const int gn = min(G, count_nodes - base);
         const uint32_t total = (uint32_t)gn * (uint32_t)pop;
+        // the group's node ids, one per lane, shared by shuffles (groups of up to 64 nodes)
+        const int32_t lane_node = lane < gn ? list[base + lane] : 0;
         int count = 0;
         for (uint32_t f0 = 0; f0 < total; f0 += 64) {
             const uint32_t f = f0 + (uint32_t)lane;
+            const uint32_t gv = divpop.div(f);
+            const int32_t shared_node = __shfl(lane_node, (int)(gv & 63u));
             bool mut = false;
             uint32_t r = 0, key = 0;
             if (f < total) {
-                const uint32_t gv = divpop.div(f);
                 const uint32_t j = f - gv * (uint32_t)pop;
-                const int32_t node = list[base + (int)gv];
+                const int32_t node = G <= 64 ? shared_node : list[base + (int)gv];
                 const u32x4 w = philox(c.seed, (uint32_t)node, j, gen, TAG_MUT);
                 mut = (uint64_t)w.a < c.thr_m;
                 r = w.b;
@@ -1170,7 +1173,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_mutate_lanes(Span sp, int cls)
         const bool staged = count + (gn * (KMAX + 3) + 1) / 2 <= MUT_LIST_CAP;
         if (staged) {
             for (int t = lane; t < gn; t += 64) {
-                const int32_t v = list[base + t];
+                const int32_t v = t < 64 ? lane_node : list[base + t];
                 const int32_t rs = g.row_ptr[v];
                 s_node[t] = v;
                 s_rs[t] = rs;
