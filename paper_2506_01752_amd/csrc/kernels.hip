@@ -1386,6 +1386,13 @@ __global__ __launch_bounds__(256) void k_mutate_wave(Span sp, int cls)
         }
         wave_lds_sync();
         constexpr int B = WaveBatch<E>::B;
+        // the node's neighbour ids: for E <= 2 read once for all its batches (a node's
+        // mutations span two batches of 8 there); wider classes reload them per batch rather
+        // than hold E more registers
+        constexpr int EH = E <= 2 ? E : 1;
+        int32_t nid[EH];
+#pragma unroll
+        for (int k = 0; k < EH; ++k) nid[k] = (E <= 2 && lane + 64 * k < d) ? nbr[lane + 64 * k] : 0;
         for (int i0 = 0; i0 < count; i0 += B) {
             const int nb = min(B, count - i0);
             int jb[B];
@@ -1395,7 +1402,12 @@ __global__ __launch_bounds__(256) void k_mutate_wave(Span sp, int cls)
 #pragma unroll
             for (int k = 0; k < E; ++k) {
                 const int p = lane + 64 * k;
-                const size_t row = p < d ? (size_t)nbr[p] * ld : 0;
+                int32_t id;
+                if constexpr (E <= 2)
+                    id = nid[k];
+                else
+                    id = p < d ? nbr[p] : 0;
+                const size_t row = (size_t)id * ld;
 #pragma unroll
                 for (int b = 0; b < B; ++b) a[b][k] = (p < d && b < nb) ? C[row + jb[b]] : INT_MAX;
             }
