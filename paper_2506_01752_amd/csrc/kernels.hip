@@ -398,8 +398,9 @@ HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, in
     p.rbits = rb;
     p.tiles = (int32_t)(((int64_t)n + (1 << rb) - 1) >> rb);
     const int counters = p.tiles * HB_CG;
-    const int budget_words = 16384 - 64;     // 64 KB of LDS: counters, staging, scan partials
-    int nb = (budget_words - counters - 1) / HB_CG;
+    // 64 KB of LDS: counters, staging (16 words a node), scan partials, row offsets (1 a node)
+    const int budget_words = 16384 - 64;
+    int nb = (budget_words - counters - 2) / (HB_CG + 1);
     nb = nb / 64 * 64;
     if (nb > BIN_MAX_NODES) nb = BIN_MAX_NODES;
     const int nb_par = (int)((n / HIST_MIN_CHUNKS) / 64 * 64);
@@ -462,6 +463,8 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(Span sp)
     uint32_t *cnt = bl;                             // [counters + 1]
     uint32_t *stage = bl + counters + 1;            // [nb * 16]
     uint32_t *wsum = stage + (size_t)p.nb * HB_CG;  // [BIN_THREADS / 64]
+    // [nb + 1] the chunk's row offsets, read once: the 16 items of a node share its degree
+    uint32_t *rpl = wsum + BIN_THREADS / 64;
     // the groups of one chunk read the same label rows (16 columns each): run them together
     const int lg = xcd_remap(lb, nblk);
     const int chunk = lg / p.ngroups, grp = lg % p.ngroups;
@@ -471,6 +474,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(Span sp)
     const int j0 = grp * HB_CG;
     const uint32_t rmask = (1u << p.rbits) - 1u;
     for (int i = threadIdx.x; i <= counters; i += blockDim.x) cnt[i] = 0;
+    for (int i = threadIdx.x; i <= nv; i += blockDim.x) rpl[i] = (uint32_t)g.row_ptr[v0 + i];
     __syncthreads();
     // items itm = 16 * (v - v0) + jl: a wave reads four 64-byte row segments
     const int items = nv * HB_CG;  // <= blockDim.x * BIN_IPT (blockDim.x >= nb)
@@ -510,8 +514,8 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(Span sp)
 #pragma unroll
     for (int k = 0; k < BIN_IPT; ++k) {
         const int itm = k * (int)blockDim.x + (int)threadIdx.x;
-        const int32_t v = v0 + (ok[k] ? (itm >> 4) : 0);
-        d[k] = (uint32_t)(g.row_ptr[v + 1] - g.row_ptr[v]);
+        const int vl = ok[k] ? (itm >> 4) : 0;
+        d[k] = rpl[vl + 1] - rpl[vl];
     }
 #pragma unroll
     for (int k = 0; k < BIN_IPT; ++k) {
@@ -1744,7 +1748,8 @@ size_t kind_lds(Kind k, const Item &it)
     case K_FIT: return sizeof(unsigned long long) * (size_t)it.fit_ld * (it.hp.enabled ? 1 : 2);
     case K_BIN:
         return it.hp.enabled ? sizeof(uint32_t) * ((size_t)it.hp.tiles * HB_CG + 1 +
-                                                   (size_t)it.hp.nb * HB_CG + BIN_THREADS / 64)
+                                                   (size_t)it.hp.nb * HB_CG + BIN_THREADS / 64 +
+                                                   (size_t)it.hp.nb + 1)
                              : 0;
     case K_HIST: return it.hp.enabled ? sizeof(uint32_t) * ((size_t)1 << it.hp.rbits) : 0;
     case K_XO:
