@@ -398,7 +398,7 @@ HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, in
     p.rbits = rb;
     p.tiles = (int32_t)(((int64_t)n + (1 << rb) - 1) >> rb);
     const int counters = p.tiles * HB_CG;
-    // 64 KB of LDS: counters, staging (16 words a node), scan partials, row offsets (1 a node)
+    // 64 KB of LDS: counters, staging (16 words a node), scan partials, degrees (1 a node)
     const int budget_words = 16384 - 64;
     int nb = (budget_words - counters - 2) / (HB_CG + 1);
     nb = nb / 64 * 64;
@@ -448,6 +448,12 @@ constexpr int BIN_THREADS = 1024;
 constexpr int BIN_IPT = BIN_MAX_NODES * HB_CG / BIN_THREADS;
 static_assert(BIN_IPT == HB_CG, "a chunk of nb nodes needs nb threads");
 
+// k_bin workgroups launched per item at most: the part's 256 CUs hold one 1024-thread
+// workgroup each (the registers of the chunk-in-registers form, with the next unit's labels
+// in flight beside this one's, leave no room for a second), and each workgroup runs unit
+// after unit.
+constexpr int BIN_RESIDENT = 256;
+
 __global__ __launch_bounds__(BIN_THREADS) void k_bin(Span sp)
 {
     int lb, nblk;
@@ -463,71 +469,86 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(Span sp)
     uint32_t *cnt = bl;                             // [counters + 1]
     uint32_t *stage = bl + counters + 1;            // [nb * 16]
     uint32_t *wsum = stage + (size_t)p.nb * HB_CG;  // [BIN_THREADS / 64]
-    // [nb + 1] the chunk's row offsets, read once: the 16 items of a node share its degree
-    uint32_t *rpl = wsum + BIN_THREADS / 64;
-    // the groups of one chunk read the same label rows (16 columns each): run them together
-    const int lg = xcd_remap(lb, nblk);
-    const int chunk = lg / p.ngroups, grp = lg % p.ngroups;
-    const int32_t v0 = chunk * p.nb;
-    const int nv = min(p.nb, g.n - v0);
-    const int cg = min(HB_CG, pop - grp * HB_CG);
-    const int j0 = grp * HB_CG;
+    uint32_t *degl = wsum + BIN_THREADS / 64;       // [nb] the chunk's degrees
     const uint32_t rmask = (1u << p.rbits) - 1u;
-    for (int i = threadIdx.x; i <= counters; i += blockDim.x) cnt[i] = 0;
-    for (int i = threadIdx.x; i <= nv; i += blockDim.x) rpl[i] = (uint32_t)g.row_ptr[v0 + i];
-    __syncthreads();
-    // items itm = 16 * (v - v0) + jl: a wave reads four 64-byte row segments
-    const int items = nv * HB_CG;  // <= blockDim.x * BIN_IPT (blockDim.x >= nb)
-    uint32_t x[BIN_IPT];
-    bool ok[BIN_IPT];
+    // Units u = chunk * ngroups + group. Blocks are dealt to the eight XCDs round-robin; the
+    // blocks of one XCD take one contiguous range of units and walk it side by side, so that
+    // at any time they hold neighbouring units: the groups of one chunk read the same label
+    // rows (16 columns each) together, through one L2.
+    const int units = p.nchunks * p.ngroups;
+    const int xcd = lb & 7, per = nblk >> 3, rem = nblk & 7;
+    const int bx = per + (xcd < rem ? 1 : 0);
+    const int l0 = xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per;
+    const int u_end = (int)((int64_t)(l0 + bx) * units / nblk);
+    int u = (int)((int64_t)l0 * units / nblk) + (lb >> 3);
+    // a unit's labels (16 items per thread, item itm = 16 * (v - v0) + jl: a wave reads four
+    // 64-byte row segments) and its nodes' degrees are loaded one unit ahead, so that the next
+    // unit's loads are in flight while this one is counted, scanned and written out
+    uint32_t xv[BIN_IPT], xn[BIN_IPT];
+    uint32_t dv = 0, dn = 0;
+    // thread t holds column t % 16 of nodes v0 + t / 16 + k * rows (blockDim.x is a multiple
+    // of 64)
+    const int col = (int)(threadIdx.x & (HB_CG - 1)), row = (int)(threadIdx.x >> 4);
+    const int rows = (int)(blockDim.x >> 4);
+    auto fetch = [&](int uu, uint32_t(&xr)[BIN_IPT], uint32_t &dr) {
+        const int chunk = uu / p.ngroups, grp = uu - chunk * p.ngroups;
+        const int32_t v0 = chunk * p.nb;
+        const int nv = min(p.nb, g.n - v0);
+        const bool colok = col < min(HB_CG, pop - grp * HB_CG);
+        const GLB int32_t *src = lab + (size_t)(v0 + row) * ld + grp * HB_CG + col;
 #pragma unroll
-    for (int k = 0; k < BIN_IPT; ++k) {
-        const int itm = k * (int)blockDim.x + (int)threadIdx.x;
-        ok[k] = itm < items && (itm & (HB_CG - 1)) < cg;
-        x[k] = ok[k] ? (uint32_t)lab[(size_t)(v0 + (itm >> 4)) * ld + j0 + (itm & (HB_CG - 1))] : 0u;
-    }
+        for (int k = 0; k < BIN_IPT; ++k)
+            xr[k] = (colok && k * rows + row < nv) ? (uint32_t)src[(size_t)(k * rows) * ld] : 0u;
+        const int t = (int)threadIdx.x;
+        dr = t < nv ? (uint32_t)(g.row_ptr[v0 + t + 1] - g.row_ptr[v0 + t]) : 0u;
+    };
+    if (u < u_end) fetch(u, xv, dv);
+    for (; u < u_end; u += bx) {
+        if (u + bx < u_end) fetch(u + bx, xn, dn);
+        const int chunk = u / p.ngroups, grp = u - chunk * p.ngroups;
+        const int32_t v0 = chunk * p.nb;
+        const int nv = min(p.nb, g.n - v0);
+        const bool colok = col < min(HB_CG, pop - grp * HB_CG);
+        for (int i = threadIdx.x; i <= counters; i += blockDim.x) cnt[i] = 0;
+        if ((int)threadIdx.x < nv) degl[threadIdx.x] = dv;
+        __syncthreads();
 #pragma unroll
-    for (int k = 0; k < BIN_IPT; ++k) {
-        const int itm = k * (int)blockDim.x + (int)threadIdx.x;
-        if (ok[k]) atomicAdd(&cnt[(x[k] >> p.rbits) * HB_CG + (itm & (HB_CG - 1))], 1u);
-    }
-    __syncthreads();
-    // exclusive scan of the counters: each thread scans a contiguous slice
-    const int per = (counters + (int)blockDim.x - 1) / (int)blockDim.x;
-    const int a = min((int)threadIdx.x * per, counters), b = min(a + per, counters);
-    uint32_t sum = 0;
-    for (int i = a; i < b; ++i) sum += cnt[i];
-    uint32_t total;
-    uint32_t acc = block_exclusive_scan(sum, wsum, &total);
-    __syncthreads();
-    for (int i = a; i < b; ++i) {
-        const uint32_t v = cnt[i];
-        cnt[i] = acc;
-        acc += v;
-    }
-    if (threadIdx.x == 0) cnt[counters] = total;
-    __syncthreads();
-    GLB uint32_t *o = off + ((size_t)chunk * p.ngroups + grp) * (size_t)(counters + 1);
-    for (int i = threadIdx.x; i <= counters; i += blockDim.x) o[i] = cnt[i];
-    __syncthreads();
-    uint32_t d[BIN_IPT];
-#pragma unroll
-    for (int k = 0; k < BIN_IPT; ++k) {
-        const int itm = k * (int)blockDim.x + (int)threadIdx.x;
-        const int vl = ok[k] ? (itm >> 4) : 0;
-        d[k] = rpl[vl + 1] - rpl[vl];
-    }
-#pragma unroll
-    for (int k = 0; k < BIN_IPT; ++k) {
-        const int itm = k * (int)blockDim.x + (int)threadIdx.x;
-        if (ok[k]) {
-            const uint32_t pos = atomicAdd(&cnt[(x[k] >> p.rbits) * HB_CG + (itm & (HB_CG - 1))], 1u);
-            stage[pos] = (x[k] & rmask) | (d[k] << p.rbits);
+        for (int k = 0; k < BIN_IPT; ++k)
+            if (colok && k * rows + row < nv) atomicAdd(&cnt[(xv[k] >> p.rbits) * HB_CG + col], 1u);
+        __syncthreads();
+        // exclusive scan of the counters: each thread scans a contiguous slice
+        const int per_t = (counters + (int)blockDim.x - 1) / (int)blockDim.x;
+        const int a = min((int)threadIdx.x * per_t, counters), b = min(a + per_t, counters);
+        uint32_t sum = 0;
+        for (int i = a; i < b; ++i) sum += cnt[i];
+        uint32_t total;
+        uint32_t acc = block_exclusive_scan(sum, wsum, &total);
+        __syncthreads();
+        for (int i = a; i < b; ++i) {
+            const uint32_t v = cnt[i];
+            cnt[i] = acc;
+            acc += v;
         }
+        if (threadIdx.x == 0) cnt[counters] = total;
+        __syncthreads();
+        GLB uint32_t *o = off + ((size_t)chunk * p.ngroups + grp) * (size_t)(counters + 1);
+        for (int i = threadIdx.x; i <= counters; i += blockDim.x) o[i] = cnt[i];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < BIN_IPT; ++k)
+            if (colok && k * rows + row < nv) {
+                const uint32_t pos = atomicAdd(&cnt[(xv[k] >> p.rbits) * HB_CG + col], 1u);
+                stage[pos] = (xv[k] & rmask) | (degl[k * rows + row] << p.rbits);
+            }
+        __syncthreads();
+        GLB uint32_t *dst = run + ((size_t)grp * p.nchunks + chunk) * ((size_t)p.nb * HB_CG);
+        for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) dst[i] = stage[i];
+        // the next unit rewrites cnt and degl only after its first barrier, which every thread
+        // reaches after its copy-out above; stage only after three more
+#pragma unroll
+        for (int k = 0; k < BIN_IPT; ++k) xv[k] = xn[k];
+        dv = dn;
     }
-    __syncthreads();
-    GLB uint32_t *dst = run + ((size_t)grp * p.nchunks + chunk) * ((size_t)p.nb * HB_CG);
-    for (uint32_t i = threadIdx.x; i < total; i += blockDim.x) dst[i] = stage[i];
 }
 
 constexpr int HIST_UNROLL = 16;
@@ -1715,7 +1736,7 @@ int32_t kind_blocks(Kind k, const Item &it)
     switch (k) {
     case K_INIT: return ceil_div(g.n, NODE_BLOCK);
     case K_FIT: return ceil_div((int64_t)ceil_div(g.n, it.fit_npw) * ((it.fit_pop + 127) / 128), FIT_WAVES);
-    case K_BIN: return it.hp.enabled ? it.hp.nchunks * it.hp.ngroups : 0;
+    case K_BIN: return it.hp.enabled ? std::min(it.hp.nchunks * it.hp.ngroups, BIN_RESIDENT) : 0;
     case K_HIST: return it.hp.enabled ? it.hp.tiles * it.fit_pop : 0;
     case K_CLEAR: {
         if (it.hp.enabled) return 0;
@@ -1749,7 +1770,7 @@ size_t kind_lds(Kind k, const Item &it)
     case K_BIN:
         return it.hp.enabled ? sizeof(uint32_t) * ((size_t)it.hp.tiles * HB_CG + 1 +
                                                    (size_t)it.hp.nb * HB_CG + BIN_THREADS / 64 +
-                                                   (size_t)it.hp.nb + 1)
+                                                   (size_t)it.hp.nb)
                              : 0;
     case K_HIST: return it.hp.enabled ? sizeof(uint32_t) * ((size_t)1 << it.hp.rbits) : 0;
     case K_XO:
