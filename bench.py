@@ -371,7 +371,8 @@ def bench_served(args):
     def serve(fifo, rate):
         """rate None: every request at t = 0 (capacity). Returns (fronts, per-request
         latency s, makespan s, stats)."""
-        srv = hp.Server(hbm_budget=budget, max_active=args.max_active, fifo=fifo)
+        srv = hp.Server(hbm_budget=budget, max_active=args.max_active, fifo=fifo,
+                        host_stage_bytes=args.host_stage_mb << 20)
         t_create = time.monotonic()
         arrivals = np.zeros(count) if rate is None else unit / rate
         tickets = [None] * count
@@ -492,6 +493,9 @@ def main():
                     help="with --served: run the capacity pass only (all requests at t = 0)")
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
+    ap.add_argument("--host-stage-mb", type=int, default=0,
+                    help="with --served: page-locked host staging per in-flight step (0: the "
+                         "library default)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (calibrates "
                          "the memory-traffic counters) and exit")
