@@ -145,3 +145,26 @@ def test_batch_many_fronts_through_one_pipelined_copy(hp):
     g = graphs[5]
     ref = oracle.run(g.row_ptr, g.col, pop_size=16, generations=3, seed=11, threads=4)
     assert same(fronts[5], ref)
+
+
+def test_batch_with_an_item_over_the_resident_binning_cap(hp):
+    """One item of |V| = 300,000 at pop 40 has over a thousand (chunk, individual group)
+    binning units, more than the binning kernel's resident workgroups, which then walk
+    several units each; beside it, items small enough for one unit per workgroup. Every
+    front equals its single run (whose histogram plan differs: a graph alone gets narrower
+    tiles) and the large item's front equals the oracle's."""
+    import torch
+    s = torch.cuda.Stream()
+    big = synth.planted_partition(300000, 12, 500, 0.4, 50, 2000, seed=3)
+    graphs = [big, synth.small_1k(), synth.fig1_graph(),
+              synth.batch_graph(dict(synth.batch_params(1, seed=4)[0], n=20000))]
+    dgs = [hp.Graph(g.row_ptr, g.col) for g in graphs]
+    p = hp.make_params(pop_size=40, generations=3, crossover_p=0.9, mutation_p=0.2,
+                       parents_per_child=4, seed=17)
+    print(f"batch n = {[g.n for g in graphs]}, pop 40", flush=True)
+    fronts = hp.run_batch(dgs, p, stream=s)
+    for i, dg in enumerate(dgs):
+        assert same(fronts[i], hp.run(dg, p, stream=s)), f"front {i} differs from its single run"
+    ref = oracle.run(big.row_ptr, big.col, pop_size=40, generations=3, crossover_p=0.9,
+                     mutation_p=0.2, parents_per_child=4, seed=17, threads=8)
+    assert same(fronts[0], ref)
