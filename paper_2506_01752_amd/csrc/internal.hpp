@@ -85,8 +85,12 @@ struct GaConst {
 // problem has at least 2^min_log2 (node, individual) pairs.
 constexpr int HB_CG = 16;  // individuals per bin group
 struct HistPlan {
-    int32_t rbits = 0;     // tile = 2^rbits label values
-    int32_t tiles = 0;     // T = ceil(n / 2^rbits)
+    // Label l goes to tile l div 2^rbits at index l mod 2^rbits (contiguous tiles, T =
+    // ceil(n / 2^rbits), tile_bits = -1), or to tile l mod T at index l div T (interleaved
+    // tiles, T = 2^tile_bits); an index is below 2^rbits either way.
+    int32_t rbits = 0;
+    int32_t tiles = 0;     // T
+    int32_t tile_bits = -1;
     int32_t nb = 0;        // nodes per pass-1 chunk
     int32_t nchunks = 0, ngroups = 0;
     bool enabled = false;
@@ -94,9 +98,11 @@ struct HistPlan {
     size_t offsets = 0;    // uint32 offsets (per chunk and group: tiles * 16 + 1)
 };
 // narrow: on small graphs, narrower tiles and smaller chunks so that pass 2 alone fills the
-// device
+// device. interleave: tiles interleave the label values, for labels that may come from a
+// narrow range (partitions handed in by a caller, e.g. community indices 0..k-1); the
+// search's own labels are node ids spread over [0, n), for which contiguous tiles suffice.
 HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, int32_t max_rbits,
-                   bool narrow);
+                   bool narrow, bool interleave = false);
 
 // One population on one graph, as the kernels see it (lives in device memory). A run is a
 // batch of one item; the batched form puts many graphs, each with its own population, into

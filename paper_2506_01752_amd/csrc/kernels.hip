@@ -374,8 +374,8 @@ __global__ __launch_bounds__(64 * FIT_WAVES) void k_fitness(Span sp)
 // the n x pop scattered additions of the plain histogram dominate the evaluation. Instead:
 //  pass 1 (k_bin): a workgroup takes nb nodes x 16 individuals, counts the (label tile,
 //   individual) bucket of every pair in LDS, scans the counts, and writes the pairs as
-//   packed words (label mod 2^rbits | deg << rbits) grouped by bucket into its own area,
-//   plus the bucket offsets;
+//   packed words (label's index within its tile | deg << rbits) grouped by bucket into its
+//   own area, plus the bucket offsets;
 //  pass 2 (k_hist): a workgroup per (tile, individual) gathers that bucket's runs from every
 //   chunk into an LDS histogram of 2^rbits counters and adds sum D_c^2 to S.
 // Every addition happens in LDS; the only global atomic is one per pass-2 workgroup.
@@ -386,9 +386,11 @@ constexpr int BIN_MAX_NODES = 1024;
 // individual) workgroups, and chunks small enough that pass 2's threads each get one
 constexpr int HIST_MIN_WGS = 512;
 constexpr int HIST_MIN_CHUNKS = 256;
+// interleaved tiles only while k_bin's counters take at most this many LDS words
+constexpr int HIST_INTERLEAVE_MAX_COUNTERS = 4096;
 
 HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, int32_t max_rbits,
-                   bool narrow)
+                   bool narrow, bool interleave)
 {
     HistPlan p;
     int rb = 0;
@@ -397,6 +399,19 @@ HistPlan hist_plan(int32_t n, int32_t pop, int32_t max_deg, int32_t min_log2, in
     while (narrow && rb > 12 && (((int64_t)n + (1 << rb) - 1) >> rb) * pop < HIST_MIN_WGS) --rb;
     p.rbits = rb;
     p.tiles = (int32_t)(((int64_t)n + (1 << rb) - 1) >> rb);
+    // Interleaved tiles (label l in tile l mod T at index l div T, T the power of two at or
+    // above the contiguous count) spread labels from a narrow range, such as community
+    // indices 0..k-1, over every tile; with contiguous tiles they would all fall in the
+    // first, whose k_hist workgroups would then do all the work. Kept contiguous where the
+    // rounding would take too much of k_bin's LDS from its chunk.
+    if (interleave) {
+        int tb = 0;
+        while ((1 << tb) < p.tiles) ++tb;
+        if ((1 << tb) * HB_CG <= HIST_INTERLEAVE_MAX_COUNTERS) {
+            p.tile_bits = tb;
+            p.tiles = 1 << tb;
+        }
+    }
     const int counters = p.tiles * HB_CG;
     // 64 KB of LDS: counters, staging (16 words a node), scan partials, degrees (1 a node)
     const int budget_words = 16384 - 64;
@@ -471,6 +486,7 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(Span sp)
     uint32_t *wsum = stage + (size_t)p.nb * HB_CG;  // [BIN_THREADS / 64]
     uint32_t *degl = wsum + BIN_THREADS / 64;       // [nb] the chunk's degrees
     const uint32_t rmask = (1u << p.rbits) - 1u;
+    const uint32_t ntiles = (uint32_t)p.tiles;
     // Units u = chunk * ngroups + group. Blocks are dealt to the eight XCDs round-robin; the
     // blocks of one XCD take one contiguous range of units and walk it side by side, so that
     // at any time they hold neighbouring units: the groups of one chunk read the same label
@@ -509,6 +525,13 @@ __global__ __launch_bounds__(BIN_THREADS) void k_bin(Span sp)
         const int32_t v0 = chunk * p.nb;
         const int nv = min(p.nb, g.n - v0);
         const bool colok = col < min(HB_CG, pop - grp * HB_CG);
+        // each label as (tile << rbits | index within its tile): with contiguous tiles, the
+        // label itself
+        if (p.tile_bits >= 0) {
+#pragma unroll
+            for (int k = 0; k < BIN_IPT; ++k)
+                xv[k] = ((xv[k] & (ntiles - 1u)) << p.rbits) | (xv[k] >> p.tile_bits);
+        }
         for (int i = threadIdx.x; i <= counters; i += blockDim.x) cnt[i] = 0;
         if ((int)threadIdx.x < nv) degl[threadIdx.x] = dv;
         __syncthreads();

@@ -1499,7 +1499,7 @@ int eval_on(const hpmocd_graph *G, const int32_t *d_labels, int32_t n_ind, void 
     it.g = dev_graph(G);
     const Tuning t;
     it.hp = hist_plan(G->n, n_ind, G->max_deg, t.hist_min_log2, t.hist_rbits,
-                      t.hist_narrow != 0);
+                      t.hist_narrow != 0, true);  // caller's labels: any range
     if (it.hp.enabled) {
         it.run = (uint32_t *)p;
         p += align_up(it.hp.entries * 4);
@@ -1574,7 +1574,7 @@ int hpmocd_eval_workspace_size(const hpmocd_graph *g, int32_t n_ind, size_t *byt
         const int32_t ld = round16(n_ind);
         const Tuning t;
         const HistPlan hp = hist_plan(g->n, n_ind, g->max_deg, t.hist_min_log2, t.hist_rbits,
-                                      t.hist_narrow != 0);
+                                      t.hist_narrow != 0, true);
         size_t b = align_up((size_t)g->n * ld * 4);  // transposed labels
         b += hp.enabled ? align_up(hp.entries * 4) + align_up(hp.offsets * 4) : align_up((size_t)g->n * ld * 4);
         b += 2 * align_up(8 * (size_t)n_ind) + 2 * align_up(8 * (size_t)n_ind);
