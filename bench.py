@@ -280,6 +280,49 @@ def bench_paper_workload(args):
     }), flush=True)
 
 
+def bench_eval(args):
+    """hpmocd_eval alone: the objectives of 100 partitions of the |V| = 1M graph handed in by
+    the caller, once labelled by node ids (each planted community by one random member) and
+    once by community indices 0..k-1, 10% of the nodes of each partition relabelled at random.
+    Device time of the evaluation kernels (the library's events), median of 5 after 2."""
+    import numpy as np
+    import torch
+
+    import paper_2506_01752_amd as hp
+    import synth
+
+    g = synth.large_1m()
+    rng = np.random.default_rng(0)
+    memb = g.membership.astype(np.int64)
+    k = int(memb.max()) + 1
+    perm = rng.permutation(g.n)
+    rep = np.zeros(k, dtype=np.int64)
+    rep[memb[perm]] = perm              # one random member per community
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    dg = hp.Graph(g.row_ptr, g.col)
+    out = {}
+    for name, base, hi in [("node_ids", rep[memb], g.n), ("community_indices", memb, k)]:
+        labs = np.empty((100, g.n), dtype=np.int32)
+        for i in range(100):
+            lab = base.copy()
+            flip = rng.random(g.n) < 0.1
+            lab[flip] = rng.integers(0, hi, int(flip.sum()))
+            labs[i] = lab
+        t = torch.from_numpy(labs).cuda()
+        ms = [hp.evaluate(dg, t, stream=stream, timing=True)[4] for _ in range(7)][2:]
+        med = float(np.median(ms))
+        out[name] = {"kernel_ms": med, "edge_evals_per_s": 100 * g.m / (med * 1e-3)}
+        print(f"# {name}: {med:.3f} ms", file=sys.stderr, flush=True)
+    print(json.dumps({
+        "metric": "fitness evaluation of given partitions (hpmocd_eval), edge-evals/s",
+        "value": out["community_indices"]["edge_evals_per_s"], "unit": "edge-evals/s",
+        "n_gpus": 1, "higher_is_better": True, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "planted_partition_1M", "n": g.n, "m": g.m, "partitions": 100,
+                   "communities": k},
+        "detail": out}), flush=True)
+
+
 def bench_quality(args):
     """Not a speed figure: how well the selected solution (Alg. 3) recovers the planted
     communities, against the best partition of the initial population."""
@@ -491,6 +534,9 @@ def main():
                     help="with --batched: time the batched call only (no sequential baseline)")
     ap.add_argument("--served-capacity-only", action="store_true",
                     help="with --served: run the capacity pass only (all requests at t = 0)")
+    ap.add_argument("--eval", action="store_true",
+                    help="fitness evaluation alone instead: 100 given partitions of the 1M "
+                         "graph, labelled by node ids and by community indices")
     ap.add_argument("--max-active", type=int, default=64)
     ap.add_argument("--hbm-budget-gb", type=float, default=200.0)
     ap.add_argument("--host-stage-mb", type=int, default=0,
@@ -522,6 +568,8 @@ def main():
         return bench_quality(args)
     if args.paper_workload:
         return bench_paper_workload(args)
+    if args.eval:
+        return bench_eval(args)
 
     import torch
 
