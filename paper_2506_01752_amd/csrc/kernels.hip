@@ -463,10 +463,10 @@ constexpr int BIN_THREADS = 1024;
 constexpr int BIN_IPT = BIN_MAX_NODES * HB_CG / BIN_THREADS;
 static_assert(BIN_IPT == HB_CG, "a chunk of nb nodes needs nb threads");
 
-// k_bin workgroups launched per item at most: the part's 256 CUs hold one 1024-thread
-// workgroup each (the registers of the chunk-in-registers form, with the next unit's labels
+// k_bin workgroups launched per item at most, for 1024-thread workgroups: the part's 256 CUs
+// hold one each (the registers of the chunk-in-registers form, with the next unit's labels
 // in flight beside this one's, leave no room for a second), and each workgroup runs unit
-// after unit.
+// after unit. Smaller workgroups (small graphs' shorter chunks) get proportionally more.
 constexpr int BIN_RESIDENT = 256;
 
 __global__ __launch_bounds__(BIN_THREADS) void k_bin(Span sp)
@@ -1759,7 +1759,12 @@ int32_t kind_blocks(Kind k, const Item &it)
     switch (k) {
     case K_INIT: return ceil_div(g.n, NODE_BLOCK);
     case K_FIT: return ceil_div((int64_t)ceil_div(g.n, it.fit_npw) * ((it.fit_pop + 127) / 128), FIT_WAVES);
-    case K_BIN: return it.hp.enabled ? std::min(it.hp.nchunks * it.hp.ngroups, BIN_RESIDENT) : 0;
+    case K_BIN: {
+        if (!it.hp.enabled) return 0;
+        // as many workgroups as fit at once: 256 of 1024 threads, more of fewer
+        const int32_t threads = (it.hp.nb + 63) / 64 * 64;
+        return std::min(it.hp.nchunks * it.hp.ngroups, BIN_RESIDENT * (BIN_THREADS / threads));
+    }
     case K_HIST: return it.hp.enabled ? it.hp.tiles * it.fit_pop : 0;
     case K_CLEAR: {
         if (it.hp.enabled) return 0;
