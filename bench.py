@@ -12,7 +12,7 @@ in the same process measures with HIP events the library records around every fi
 launch (kernels launched one by one); that pass also gives the per-kernel-group breakdown
 and the roofline figures.
 
-Prints one JSON line. ``--gpus N`` with N > 1 is refused: this build targets one GPU.
+Prints one JSON line. ``--gpus N`` with N > 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -557,7 +557,7 @@ def main():
         print(json.dumps({"copy_probe_bytes": a.numel()}))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.batched:
