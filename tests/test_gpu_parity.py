@@ -90,6 +90,32 @@ def test_eval_matches_oracle(hp, stream, gname, n_ind):
         assert bits([f1[i]])[0] == bits([r1])[0] and bits([f2[i]])[0] == bits([r2])[0]
 
 
+def test_eval_community_indices_1m(hp, stream):
+    """|V| = 1,000,000, 16 partitions: 8 labelled by planted-community indices 0..k-1 (a narrow
+    label range, spread by the evaluation's interleaved histogram tiles) and 8 by node ids,
+    each with 10% of its nodes relabelled at random; every objective equals the oracle's."""
+    import torch
+    g = synth.large_1m()
+    rng = np.random.default_rng(23)
+    memb = g.membership.astype(np.int64)
+    k = int(memb.max()) + 1
+    rows = []
+    for i in range(16):
+        lab = memb.copy() if i < 8 else rng.permutation(g.n)[memb]
+        hi = k if i < 8 else g.n
+        flip = rng.random(g.n) < 0.1
+        lab[flip] = rng.integers(0, hi, int(flip.sum()))
+        rows.append(lab)
+    labs = np.stack(rows).astype(np.int32)
+    say(f"eval large_1m n_ind=16, {k} communities")
+    A, S, f1, f2 = hp.evaluate(hp.Graph(g.row_ptr, g.col), torch.from_numpy(labs).cuda(),
+                               stream=stream)
+    for i in range(16):
+        ra, rs, r1, r2 = oracle.evaluate(g.row_ptr, g.col, labs[i])
+        assert (A[i], S[i]) == (ra, rs), i
+        assert bits([f1[i]])[0] == bits([r1])[0] and bits([f2[i]])[0] == bits([r2])[0]
+
+
 @pytest.mark.parametrize("bad", [-1, 1000, 2**31 - 1])
 def test_eval_out_of_range_label_is_an_error(hp, stream, bad):
     """A label outside [0, n) is reported as ERR_RANGE (the kernel that reads the labels
