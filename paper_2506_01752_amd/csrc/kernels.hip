@@ -1684,39 +1684,46 @@ hipError_t launch_extract(int32_t n, int32_t ld, int32_t pop, const int32_t *poo
     return hipGetLastError();
 }
 
-// rows [n_ind][n] -> node-major [n][ld], 32x32 tiles through LDS. With `bad`, a label
-// outside [0, n) is stored as 0 (the kernels downstream index by label) and *bad set to 1.
-__global__ void k_transpose_in(const int32_t *__restrict__ rows, int32_t n, int32_t n_ind,
-                               int32_t ld, int32_t *__restrict__ out, int32_t *__restrict__ bad)
+// rows [n_ind][n] -> node-major [n][ld] through LDS, 64 individuals x 64 nodes per 256-thread
+// workgroup: each wave reads one individual's 256-byte run of 64 labels per step and writes
+// one node's 64 columns. With `bad`, a label outside [0, n) is stored as 0 (the kernels
+// downstream index by label) and *bad set to 1.
+__global__ __launch_bounds__(256) void k_transpose_in(const int32_t *__restrict__ rows, int32_t n,
+                                                      int32_t n_ind, int32_t ld,
+                                                      int32_t *__restrict__ out,
+                                                      int32_t *__restrict__ bad)
 {
-    __shared__ int tile[32][33];
-    const int64_t v0 = (int64_t)blockIdx.x * 32;
-    const int i0 = blockIdx.y * 32;
-    for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    __shared__ int tile[64][65];
+    const int64_t v0 = (int64_t)blockIdx.x * 64;
+    const int i0 = blockIdx.y * 64;
+    const int lane = (int)(threadIdx.x & 63), w = (int)(threadIdx.x >> 6);
+    bool seen_bad = false;
+    for (int r = w; r < 64; r += 4) {
         const int i = i0 + r;
-        const int64_t v = v0 + threadIdx.x;
+        const int64_t v = v0 + lane;
         if (i < n_ind && v < n) {
             int32_t x = rows[(size_t)i * n + v];
             if (bad && (x < 0 || x >= n)) {
-                *bad = 1;
+                seen_bad = true;
                 x = 0;
             }
-            tile[r][threadIdx.x] = x;
+            tile[r][lane] = x;
         }
     }
+    if (seen_bad) *bad = 1;
     __syncthreads();
-    for (int r = threadIdx.y; r < 32; r += blockDim.y) {
+    for (int r = w; r < 64; r += 4) {
         const int64_t v = v0 + r;
-        const int i = i0 + threadIdx.x;
-        if (i < n_ind && v < n) out[(size_t)v * ld + i] = tile[threadIdx.x][r];
+        const int i = i0 + lane;
+        if (i < n_ind && v < n) out[(size_t)v * ld + i] = tile[lane][r];
     }
 }
 
 hipError_t launch_transpose_in(const int32_t *rows, int32_t n, int32_t n_ind, int32_t ld,
                                int32_t *out, int32_t *bad, hipStream_t s)
 {
-    dim3 grid((unsigned)((n + 31) / 32), (unsigned)((n_ind + 31) / 32));
-    k_transpose_in<<<grid, dim3(32, 8), 0, s>>>(rows, n, n_ind, ld, out, bad);
+    dim3 grid((unsigned)((n + 63) / 64), (unsigned)((n_ind + 63) / 64));
+    k_transpose_in<<<grid, 256, 0, s>>>(rows, n, n_ind, ld, out, bad);
     return hipGetLastError();
 }
 
